@@ -1,0 +1,289 @@
+#!/usr/bin/env python3
+"""Benchmark of the BSI hot path on one MI355X.
+
+A step is one pass of the hot path over one batch of synthetic input: forward BSI
+(control grid -> field, Eq. 1) followed by the adjoint (dfield -> control-grid
+gradient) on a 512 x 512 x 256 volume at spacing 5 (grid 106 x 106 x 55 x 3,
+N(0, 3) box-filtered; dfield N(0, 1)), with every input resident in HBM before
+the timed region.  value = voxels / (time per step) in GVoxel/s.
+
+Printed as ONE JSON line on stdout (logs go to stderr), with:
+  roofline      the dominant kernel's algorithmic bytes / its mean duration
+                (HIP events on the launch stream) against 8 TB/s, and the HBM
+                traffic measured by rocprofv3 counters when the committed
+                measurement matches the current kernel sources;
+  cpu_baseline  the FP64 oracle (forward + adjoint) on the first 128 z-planes of
+                the same volume, on the host's cores;
+  extras        forward at spacings 3 and 8, the adjoint alone at 256^3
+                (MALL flushed between repetitions), the 32-volume batched
+                graph launch against per-volume launches, and one SSD
+                registration iteration at 256 x 256 x 160.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GVoxel/s BSI fwd+adjoint (fp32), % HBM peak; batched vs per-volume, 1 GPU"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = {
+    "fwd_kernel": ["paper_2004_05962_amd/csrc/bsi_device.h", "paper_2004_05962_amd/csrc/forward.hip"],
+    "adj_pass1_kernel": ["paper_2004_05962_amd/csrc/bsi_device.h", "paper_2004_05962_amd/csrc/adjoint_device.h",
+                         "paper_2004_05962_amd/csrc/adjoint.hip"],
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash(kernel):
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter runs, or None when
+    they were taken on other sources or another workload."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            data = json.load(f)
+        rec = data[kernel]
+    except (OSError, KeyError, ValueError):
+        return None
+    if rec.get("src_hash") != source_hash(kernel) or rec.get("workload") != workload:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def median(xs):
+    return float(np.median(np.asarray(xs, np.float64)))
+
+
+def time_events(torch, fn, reps, flush=None):
+    """Durations (ms) of fn() between HIP events on the current stream."""
+    out = []
+    for _ in range(reps):
+        if flush is not None:
+            flush()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        out.append(a.elapsed_time(b))
+    return out
+
+
+def cpu_baseline(grid_np, dfield_np, dims, spacing, planes=128):
+    """FP64 oracle, forward + adjoint, on the first `planes` z-planes."""
+    import oracle
+    d = spacing[2]
+    sub_dims = (dims[0], dims[1], planes)
+    gz = -(-planes // d) + 3
+    g = grid_np[:gz]
+    y = dfield_np[:planes]
+    t0 = time.perf_counter()
+    oracle.forward(g, sub_dims, spacing)
+    t1 = time.perf_counter()
+    oracle.adjoint(y, sub_dims, spacing)
+    t2 = time.perf_counter()
+    vox = dims[0] * dims[1] * planes
+    return {"value": vox / (t2 - t0) / 1e9, "unit": "GVoxel/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"first {planes} of {dims[2]} z-planes ({vox / 1e6:.1f} M voxels), forward {t1 - t0:.2f} s "
+                      f"(OpenMP) + adjoint {t2 - t1:.2f} s (serial scatter), FP64"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--quick", action="store_true", help="main step only: no extras, no CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the hot path here runs on a single MI355X; "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+    rank = int(os.environ.get("RANK", "0"))
+
+    import torch
+    import paper_2004_05962_amd as bsi
+    import workloads
+
+    torch.cuda.set_device(0)
+    log("setup: 512x512x256 spacing 5")
+    case = workloads.cfg2(5)
+    dims, spacing = case["dims"], case["spacing"]
+    V = dims[0] * dims[1] * dims[2]
+    gx, gy, gz = bsi.bsi_grid_dims(dims, spacing)
+    G = gx * gy * gz
+    dfield_np = workloads.random_field(dims, 1.0, seed=1102)
+    grid = torch.from_numpy(case["grid"]).cuda()
+    dfield = torch.from_numpy(dfield_np).cuda()
+    field = torch.empty(bsi.field_shape(dims), device="cuda")
+    grad = torch.empty(bsi.grid_shape(dims, spacing), device="cuda")
+    ws = torch.empty(bsi.bsi_adjoint_workspace_size(dims, spacing), dtype=torch.uint8, device="cuda")
+
+    def step():
+        bsi.bsi_forward(grid, dims, spacing, field)
+        bsi.bsi_adjoint(dfield, dims, spacing, grad, ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e in ev:
+        e[0].record()
+        bsi.bsi_forward(grid, dims, spacing, field)
+        e[1].record()
+        bsi.bsi_adjoint(dfield, dims, spacing, grad, ws)
+        e[2].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    fwd_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    adj_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    ms_per_step = wall * 1e3 / args.steps
+    value = V / (ms_per_step * 1e-3) / 1e9
+
+    fwd_bytes = 12 * V + 12 * G
+    adj_bytes = 12 * V + 12 * G
+    workload = "512x512x256 d5"
+    kern, ms, nbytes = ("fwd_kernel", fwd_ms, fwd_bytes) if fwd_ms >= adj_ms else ("adj_pass1_kernel", adj_ms, adj_bytes)
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kern, workload),
+                "kernel": kern, "algorithmic_bytes": nbytes, "mean_ms": round(ms, 4)}
+    other = {"forward_ms": round(fwd_ms, 4), "adjoint_ms": round(adj_ms, 4),
+             "forward_hbm_frac": round(fwd_bytes / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+             "adjoint_hbm_frac": round(adj_bytes / (adj_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+             "forward_gvoxel_s": round(V / (fwd_ms * 1e-3) / 1e9, 2),
+             "adjoint_gvoxel_s": round(V / (adj_ms * 1e-3) / 1e9, 2)}
+    log("main:", json.dumps(other))
+
+    extras = {}
+    if not args.quick:
+        extras = run_extras(torch, bsi, workloads)
+    cpu = None
+    if not args.quick and not args.no_cpu and rank == 0:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(case["grid"], dfield_np, dims, spacing)
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "GVoxel/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "BSI forward + adjoint, 512x512x256 voxels, spacing 5, grid 106x106x55x3",
+                   "global_batch": 1, "voxels": V, "spacing": list(spacing), "parallelism": "single GPU"},
+        "roofline": roofline, "cpu_baseline": cpu, "breakdown": other, "extras": extras,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_extras(torch, bsi, workloads):
+    ex = {}
+    flush_buf = torch.empty(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB, > 256 MB MALL
+
+    def flush():
+        flush_buf.zero_()
+
+    # forward at the other clinical spacings
+    for d in (3, 8):
+        c = workloads.cfg2(d)
+        dims, sp = c["dims"], c["spacing"]
+        V = dims[0] * dims[1] * dims[2]
+        gx, gy, gz = bsi.bsi_grid_dims(dims, sp)
+        g = torch.from_numpy(c["grid"]).cuda()
+        f = torch.empty(bsi.field_shape(dims), device="cuda")
+        for _ in range(3):
+            bsi.bsi_forward(g, dims, sp, f)
+        ms = median(time_events(torch, lambda: bsi.bsi_forward(g, dims, sp, f), 20))
+        nb = 12 * V + 12 * gx * gy * gz
+        ex[f"forward_512x512x256_d{d}"] = {"ms": round(ms, 4), "gvoxel_s": round(V / ms / 1e6, 2),
+                                           "hbm_frac": round(nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        log(f"forward d{d}:", ex[f"forward_512x512x256_d{d}"])
+        del g, f
+
+    # adjoint alone at 256^3 (its dfield fits the MALL: flush between repetitions)
+    c = workloads.cfg3()
+    dims, sp = c["dims"], c["spacing"]
+    V = dims[0] * dims[1] * dims[2]
+    gx, gy, gz = bsi.bsi_grid_dims(dims, sp)
+    y = torch.from_numpy(c["dfield"]).cuda()
+    out = torch.empty(bsi.grid_shape(dims, sp), device="cuda")
+    ws = torch.empty(bsi.bsi_adjoint_workspace_size(dims, sp), dtype=torch.uint8, device="cuda")
+    for _ in range(3):
+        bsi.bsi_adjoint(y, dims, sp, out, ws)
+    ms = median(time_events(torch, lambda: bsi.bsi_adjoint(y, dims, sp, out, ws), 20, flush=flush))
+    nb = 12 * V + 12 * gx * gy * gz
+    ex["adjoint_256cubed_d5"] = {"ms": round(ms, 4), "gvoxel_s": round(V / ms / 1e6, 2),
+                                 "hbm_frac": round(nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    log("adjoint 256^3:", ex["adjoint_256cubed_d5"])
+    del y, out, ws
+
+    # batched: 32 uneven volumes, forward + adjoint, one graph vs per-volume launches
+    dims_l, sp_l = workloads.cfg5_geometry()
+    grids, dfields, fields, grads = [], [], [], []
+    for i, (d, s) in enumerate(zip(dims_l, sp_l)):
+        g, y = workloads.cfg5_volume(tuple(d), tuple(s), i)
+        grids.append(torch.from_numpy(g).cuda())
+        dfields.append(torch.from_numpy(y).cuda())
+        fields.append(torch.empty(bsi.field_shape(d), device="cuda"))
+        grads.append(torch.empty(bsi.grid_shape(d, s), device="cuda"))
+    vox = int(sum(int(np.prod(d)) for d in dims_l))
+    plan = bsi.BatchPlan(dims_l, sp_l)
+    plan.bind(grids, fields, dfields, grads)
+    chosen, nsched = plan.tune()
+    # the legacy null stream cannot be captured: capture on a side stream, replay on the current one
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    plan.capture(side)
+    torch.cuda.current_stream().wait_stream(side)
+    for _ in range(3):
+        plan.launch()
+        plan.run_separate()
+    t_graph = median(time_events(torch, plan.launch, 20))
+    t_sep = median(time_events(torch, plan.run_separate, 20))
+    ex["batched_32_volumes"] = {"voxels": vox, "graph_ms": round(t_graph, 4), "separate_ms": round(t_sep, 4),
+                                "speedup": round(t_sep / t_graph, 3), "graph_gvoxel_s": round(vox / t_graph / 1e6, 2),
+                                "schedule": chosen, "schedules": nsched}
+    log("batched:", ex["batched_32_volumes"])
+    plan.close()
+    del grids, dfields, fields, grads
+
+    # one SSD registration iteration at 256 x 256 x 160 (moving image made on the GPU)
+    c = workloads.cfg4()
+    dims, sp = c["dims"], c["spacing"]
+    fixed = torch.from_numpy(c["fixed"]).cuda()
+    Ttrue = bsi.forward(torch.from_numpy(c["grid_true"]).cuda(), dims, sp)
+    moving = torch.empty_like(fixed)
+    bsi.bsi_warp(Ttrue, fixed, dims, moving)
+    reg = bsi.SSDRegistration(fixed, moving, sp, max_steps=64)
+    reg.auto_eta()
+    reg.run(3)
+    ms = median(time_events(torch, reg.step, 20))
+    V = dims[0] * dims[1] * dims[2]
+    ex["registration_iteration_256x256x160_d5"] = {"ms": round(ms, 4), "gvoxel_s": round(V / ms / 1e6, 2),
+                                                   "loss_first": float(reg.losses[0]), "loss_last": float(reg.losses[reg.step_index - 1])}
+    log("registration:", ex["registration_iteration_256x256x160_d5"])
+    return ex
+
+
+if __name__ == "__main__":
+    main()

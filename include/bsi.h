@@ -1,0 +1,182 @@
+/*
+ * bsi.h -- C ABI of libbsi: cubic B-spline interpolation (BSI) of a 3-D
+ * free-form-deformation control grid on AMD Instinct MI355X (gfx950).
+ *
+ * The operation (paper: Sec. 2.1, Eq. 1).  For every voxel (x, y, z) of a volume
+ * of nx x ny x nz voxels and a control grid with integer spacings dx, dy, dz
+ * (in voxels, grid aligned to the voxels, Sec. 3.4):
+ *
+ *   T(x,y,z) = sum_{l,m,n=0..3} B_l(u) B_m(v) B_n(w) phi[k+n][j+m][i+l]
+ *
+ *   i = floor(x/dx), u = x/dx - floor(x/dx)      (likewise j, v and k, w)
+ *   B0 = (1-u)^3/6, B1 = (3u^3-6u^2+4)/6, B2 = (-3u^3+3u^2+3u+1)/6, B3 = u^3/6
+ *
+ * Indices here are storage indices: the paper's control-point index plus one,
+ * so that every index is >= 0.  The grid therefore has g = ceil(n/d) + 3 points
+ * per axis (bsi_grid_dims).
+ *
+ * Layouts (row-major, component last; components are the x, y, z displacement):
+ *   grid, grid_grad  : float [gz][gy][gx][3]
+ *   field, dfield    : float [nz][ny][nx][3]
+ *   images           : float [nz][ny][nx]
+ *   dims    = {nx, ny, nz},  spacing = {dx, dy, dz}  (host int32 arrays)
+ *
+ * Common rules for every entry point below unless it says otherwise:
+ *   - Buffer pointers are DEVICE pointers owned by the caller.  The library
+ *     never frees or retains them; the buffers must not overlap.  4-byte
+ *     alignment is enough.
+ *   - dims/spacing/out-params are HOST pointers.
+ *   - Work is enqueued asynchronously on `stream` (0 = the null stream) of the
+ *     current HIP device; no call synchronises the host.
+ *   - Arithmetic is FP32.  For a fixed build the result bits are a function of
+ *     the inputs only (no atomics, fixed summation order): reruns, tuning
+ *     choices, batched and per-volume launches give identical bits.
+ *   - Return 0 on success or a negative BSI_ERR_* code; bsi_last_error() then
+ *     holds a message.  No exception crosses the ABI.
+ */
+#ifndef BSI_H
+#define BSI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BSI_OK 0
+#define BSI_ERR_INVALID_ARG (-1) /* null pointer, n < 1, d < 1, bad size     */
+#define BSI_ERR_UNSUPPORTED (-2) /* d > BSI_MAX_SPACING, or a size too large  */
+#define BSI_ERR_HIP (-3)         /* a HIP call failed; see bsi_last_error()  */
+#define BSI_ERR_NO_DEVICE (-4)   /* no HIP device is visible                 */
+#define BSI_ERR_NOMEM (-5)       /* allocation of a batched plan failed      */
+
+#define BSI_MAX_SPACING 64       /* largest supported spacing, per axis      */
+#define BSI_MAX_DIM (1 << 20)    /* largest supported voxel count per axis   */
+
+/* Version of this ABI (major * 10000 + minor * 100 + patch). */
+int32_t bsi_version(void);
+
+/* Message for the last failed call on this host thread ("" if none). */
+const char* bsi_last_error(void);
+
+/* Control-grid size for a volume: out_g[a] = ceil(dims[a]/spacing[a]) + 3.
+   Host-only; needs no device.  Errors: INVALID_ARG, UNSUPPORTED. */
+int32_t bsi_grid_dims(const int32_t dims[3], const int32_t spacing[3], int32_t out_g[3]);
+
+/* Forward BSI (Eq. 1): field[z][y][x][:] = T(x, y, z) for every voxel.
+   grid: [gz][gy][gx][3] read-only; field: [nz][ny][nx][3] fully overwritten.
+   Errors: INVALID_ARG, UNSUPPORTED, NO_DEVICE, HIP. */
+int32_t bsi_forward(const float* grid, const int32_t dims[3], const int32_t spacing[3],
+                    float* field, hipStream_t stream);
+
+/* Scratch size in bytes that bsi_adjoint needs for this geometry (host-only). */
+int32_t bsi_adjoint_workspace_size(const int32_t dims[3], const int32_t spacing[3],
+                                   size_t* bytes);
+
+/* Adjoint of Eq. 1 (its exact transpose; not in the paper): for every control
+   point a,
+     grid_grad[a] = sum over voxels x whose 4x4x4 window contains a of
+                    B_{a_x-i}(u) B_{a_y-j}(v) B_{a_z-k}(w) * dfield[x].
+   dfield: [nz][ny][nx][3] read-only; grid_grad: [gz][gy][gx][3] OVERWRITTEN
+   (not accumulated).  workspace: device scratch of at least
+   bsi_adjoint_workspace_size() bytes, owned by the caller, contents ignored on
+   entry and undefined on exit; it must not be shared by calls that may run
+   concurrently.  Deterministic gather in a fixed order, no atomics.
+   Errors: INVALID_ARG (also when workspace_bytes is too small), UNSUPPORTED,
+   NO_DEVICE, HIP. */
+int32_t bsi_adjoint(const float* dfield, const int32_t dims[3], const int32_t spacing[3],
+                    float* grid_grad, void* workspace, size_t workspace_bytes,
+                    hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * SSD registration step (the FFD loop of Sec. 6 with a sum-of-squared-
+ * differences similarity standing in for the paper's NiftyReg measure).
+ * p(x) = x + T(x) in voxel units, formed in FP32; trilinear interpolation with
+ * corners on voxel centres and p clamped to [0, n-1] per axis; at an exact
+ * integer p the cell [p, p+1] is used.
+ * ------------------------------------------------------------------------- */
+
+/* out[z][y][x] = image sampled at p(x).  field: [nz][ny][nx][3]; image, out:
+   [nz][ny][nx].  Errors: INVALID_ARG, UNSUPPORTED, NO_DEVICE, HIP. */
+int32_t bsi_warp(const float* field, const float* image, const int32_t dims[3], float* out,
+                 hipStream_t stream);
+
+/* Scratch size in bytes that bsi_ssd_grad needs for this volume (host-only). */
+int32_t bsi_ssd_workspace_size(const int32_t dims[3], size_t* bytes);
+
+/* SSD loss and its gradient with respect to the displacement field:
+     W = moving(p(x)),  r = W - fixed,  loss[0] = sum_x r^2 (FP32, fixed order),
+     dfield[x][c] = 2 r dW/dp_c, and 0 where p_c <= 0 or p_c >= n_c - 1.
+   field: [nz][ny][nx][3]; moving, fixed: [nz][ny][nx]; dfield: [nz][ny][nx][3]
+   overwritten; loss: one device float, overwritten.  workspace as for
+   bsi_adjoint, of bsi_ssd_workspace_size() bytes.
+   Errors: INVALID_ARG, UNSUPPORTED, NO_DEVICE, HIP. */
+int32_t bsi_ssd_grad(const float* field, const float* moving, const float* fixed,
+                     const int32_t dims[3], float* dfield, float* loss, void* workspace,
+                     size_t workspace_bytes, hipStream_t stream);
+
+/* Gradient-descent update grid[i] -= eta * grad[i] for i < count (count = number
+   of floats).  Errors: INVALID_ARG, NO_DEVICE, HIP. */
+int32_t bsi_descent_step(float* grid, const float* grad, float eta, int64_t count,
+                         hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched forward + adjoint of many volumes of different sizes and spacings in
+ * persistent launches (not in the paper).  A plan fixes the geometry at
+ * creation, binds the per-volume buffers once, and can capture the whole
+ * forward + adjoint into one HIP graph that is replayed with one launch.
+ * Results are bit-identical to bsi_forward / bsi_adjoint on each volume.
+ * A plan belongs to the device that was current at bsi_batch_create; every
+ * call on it must run with that device current.
+ * ------------------------------------------------------------------------- */
+typedef struct bsi_batch bsi_batch;
+
+/* Create a plan for `count` volumes; dims3xN / spacing3xN hold count triples
+   (host).  Allocates the plan's descriptor table and adjoint scratch on the
+   current device.  Errors: INVALID_ARG, UNSUPPORTED, NO_DEVICE, NOMEM, HIP. */
+int32_t bsi_batch_create(int32_t count, const int32_t* dims3xN, const int32_t* spacing3xN,
+                         bsi_batch** out);
+
+/* Bind device buffers (host arrays of `count` device pointers each).  grids and
+   fields are used by the forward, dfields and grid_grads by the adjoint; pass
+   NULL for a whole pass to leave it out.  Invalidates a captured graph. */
+int32_t bsi_batch_bind(bsi_batch* plan, const float* const* grids, float* const* fields,
+                       const float* const* dfields, float* const* grid_grads);
+
+/* Time the candidate schedules (persistent grid size, work order) on `stream`
+   with the bound buffers and keep the fastest.  The choice is stored in the
+   JSON file named by the environment variable BSI_TUNE_CACHE (if set) and read
+   back by later plans with the same geometry.  BSI_FORCE_CONFIG=<index> skips
+   timing.  Synchronises `stream`.  Schedules never change result bits. */
+int32_t bsi_batch_tune(bsi_batch* plan, hipStream_t stream);
+
+/* Index of the schedule the plan uses, and the number of candidates. */
+int32_t bsi_batch_config(const bsi_batch* plan, int32_t* index, int32_t* count);
+
+/* Enqueue the persistent forward and adjoint kernels directly on `stream`. */
+int32_t bsi_batch_run(bsi_batch* plan, hipStream_t stream);
+
+/* Reference schedule: one bsi_forward + bsi_adjoint launch pair per volume,
+   enqueued back to back on `stream` (same kernels' arithmetic, same bits). */
+int32_t bsi_batch_run_separate(bsi_batch* plan, hipStream_t stream);
+
+/* Capture bsi_batch_run into a HIP graph (stream capture on `stream`) and
+   instantiate it.  Errors: INVALID_ARG (nothing bound), HIP. */
+int32_t bsi_batch_capture(bsi_batch* plan, hipStream_t stream);
+
+/* Replay the captured graph with one hipGraphLaunch on `stream`.
+   Errors: INVALID_ARG (no graph captured), HIP. */
+int32_t bsi_batch_launch(bsi_batch* plan, hipStream_t stream);
+
+/* Release the plan, its graph and its device memory (synchronises the device
+   that owns it).  NULL is ignored. */
+void bsi_batch_destroy(bsi_batch* plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSI_H */

@@ -1,0 +1,49 @@
+// Host-side internals of libbsi: error reporting, device state and launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "bsi.h"
+#include "bsi_device.h"
+
+namespace bsi {
+
+// Thread-local last-error message (returned by bsi_last_error).
+void set_error(const std::string& msg);
+void clear_error();
+int32_t hip_fail(hipError_t e, const char* what);  // records and returns BSI_ERR_HIP
+
+// Current device, checking that one exists (BSI_ERR_NO_DEVICE otherwise).
+int32_t current_device(int* dev);
+
+// Basis table of every spacing 1..kMaxSpacing on device `dev` (uploaded on the
+// first call per device, then cached for the life of the process).
+int32_t lut_device_ptr(int dev, const float** out);
+
+// Host-side geometry helpers.
+int32_t make_geom(const int32_t dims[3], const int32_t spacing[3], VolGeom* g);
+AdjGeom make_adj_geom(const VolGeom& g);
+size_t adj_workspace_bytes(const AdjGeom& a);
+
+// Forward launch shape (workgroups of kFwdRows waves; z split into chunks).
+struct FwdLaunch {
+  int nbx, nby, nbz, zchunk;
+};
+constexpr int kFwdRows = 4;
+FwdLaunch make_fwd_launch(const VolGeom& g);
+
+hipError_t launch_forward(const float* grid, float* field, const VolGeom& g, const float* lut,
+                          hipStream_t s);
+hipError_t launch_adjoint(const float* dfield, float* grad, const AdjGeom& a, const float* lut,
+                          float* part, hipStream_t s);
+hipError_t launch_warp(const float* field, const float* image, const VolGeom& g, float* out,
+                       hipStream_t s);
+size_t ssd_partial_count(const VolGeom& g);
+hipError_t launch_ssd_grad(const float* field, const float* moving, const float* fixed,
+                           const VolGeom& g, float* dfield, float* loss, float* partials,
+                           hipStream_t s);
+hipError_t launch_descent(float* grid, const float* grad, float eta, int64_t count, hipStream_t s);
+
+}  // namespace bsi

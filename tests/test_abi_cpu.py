@@ -1,0 +1,123 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol, and
+validates arguments with the documented error codes before touching a device.
+
+No compute call is made here (there is no GPU on this host)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT, has_gpu
+
+import paper_2004_05962_amd as bsi
+from paper_2004_05962_amd import _lib
+
+HEADER = os.path.join(ROOT, "include", "bsi.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bsi_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_symbols()
+    assert len(names) >= 19
+    L = _lib.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_version_and_error_string():
+    assert bsi.bsi_version() == 10000
+    assert isinstance(bsi.bsi_last_error(), str)
+
+
+@pytest.mark.parametrize("dims,spacing,expect", [
+    ((64, 64, 64), (5, 5, 5), (16, 16, 16)),
+    ((512, 512, 256), (3, 3, 3), (174, 174, 89)),
+    ((512, 512, 256), (5, 5, 5), (106, 106, 55)),
+    ((512, 512, 256), (8, 8, 8), (67, 67, 35)),
+    ((256, 256, 160), (5, 5, 5), (55, 55, 35)),
+    ((12, 12, 12), (5, 5, 5), (6, 6, 6)),
+    ((1, 1, 1), (64, 64, 64), (4, 4, 4)),
+])
+def test_grid_dims(dims, spacing, expect):
+    assert bsi.bsi_grid_dims(dims, spacing) == expect
+
+
+@pytest.mark.parametrize("dims,spacing,code", [
+    ((0, 4, 4), (1, 1, 1), _lib.BSI_ERR_INVALID_ARG),
+    ((4, -1, 4), (1, 1, 1), _lib.BSI_ERR_INVALID_ARG),
+    ((4, 4, 4), (1, 0, 1), _lib.BSI_ERR_INVALID_ARG),
+    ((4, 4, 4), (1, 1, 65), _lib.BSI_ERR_UNSUPPORTED),
+    ((1 << 21, 4, 4), (1, 1, 1), _lib.BSI_ERR_UNSUPPORTED),
+])
+def test_bad_geometry(dims, spacing, code):
+    with pytest.raises(bsi.BSIError) as e:
+        bsi.bsi_grid_dims(dims, spacing)
+    assert e.value.code == code
+    assert bsi.bsi_last_error()
+
+
+def _call(name, *args):
+    return getattr(_lib.lib(), name)(*args)
+
+
+def _t(v):
+    return _lib._triple(v, "t")
+
+
+P = ctypes.c_void_p(256)  # a non-null placeholder; never dereferenced by the checks below
+NULL = ctypes.c_void_p(0)
+
+
+def test_null_pointers_rejected_before_device():
+    d, s = _t((8, 8, 8)), _t((2, 2, 2))
+    assert _call("bsi_forward", NULL, d, s, P, NULL) == _lib.BSI_ERR_INVALID_ARG
+    assert _call("bsi_forward", P, d, s, NULL, NULL) == _lib.BSI_ERR_INVALID_ARG
+    assert _call("bsi_adjoint", P, d, s, P, NULL, 1 << 30, NULL) == _lib.BSI_ERR_INVALID_ARG
+    assert _call("bsi_warp", NULL, P, d, P, NULL) == _lib.BSI_ERR_INVALID_ARG
+    assert _call("bsi_ssd_grad", P, P, P, d, P, NULL, P, 1 << 30, NULL) == _lib.BSI_ERR_INVALID_ARG
+    assert _call("bsi_descent_step", NULL, P, ctypes.c_float(1.0), 4, NULL) == _lib.BSI_ERR_INVALID_ARG
+    assert _call("bsi_descent_step", P, P, ctypes.c_float(1.0), -1, NULL) == _lib.BSI_ERR_INVALID_ARG
+    assert "non-null" in bsi.bsi_last_error() or "count" in bsi.bsi_last_error()
+
+
+def test_workspace_size_checked_before_device():
+    d, s = _t((40, 30, 20)), _t((5, 5, 5))
+    need = bsi.bsi_adjoint_workspace_size((40, 30, 20), (5, 5, 5))
+    assert need > 0
+    assert _call("bsi_adjoint", P, d, s, P, P, need - 1, NULL) == _lib.BSI_ERR_INVALID_ARG
+    assert "workspace too small" in bsi.bsi_last_error()
+    ssd = bsi.bsi_ssd_workspace_size((40, 30, 20))
+    assert _call("bsi_ssd_grad", P, P, P, d, P, P, P, ssd - 1, NULL) == _lib.BSI_ERR_INVALID_ARG
+
+
+def test_batch_argument_checks():
+    plan = ctypes.c_void_p()
+    n = ctypes.c_int32 * 3
+    assert _call("bsi_batch_create", 0, n(4, 4, 4), n(1, 1, 1), ctypes.byref(plan)) == _lib.BSI_ERR_INVALID_ARG
+    assert _call("bsi_batch_create", 1, n(0, 4, 4), n(1, 1, 1), ctypes.byref(plan)) == _lib.BSI_ERR_INVALID_ARG
+    assert _call("bsi_batch_run", NULL, NULL) == _lib.BSI_ERR_INVALID_ARG
+    assert _call("bsi_batch_launch", NULL, NULL) == _lib.BSI_ERR_INVALID_ARG
+    _call("bsi_batch_destroy", NULL)  # NULL is ignored
+
+
+@pytest.mark.skipif(has_gpu(), reason="checks the no-device path")
+def test_no_device_reported():
+    d, s = _t((8, 8, 8)), _t((2, 2, 2))
+    assert _call("bsi_forward", P, d, s, P, NULL) == _lib.BSI_ERR_NO_DEVICE
+    assert "no HIP device" in bsi.bsi_last_error()
+    plan = ctypes.c_void_p()
+    assert _call("bsi_batch_create", 1, d, s, ctypes.byref(plan)) == _lib.BSI_ERR_NO_DEVICE
+
+
+def test_workspace_sizes_follow_brick_geometry():
+    # the adjoint's partials cost a few % of the dfield at the benchmark sizes
+    for dims, sp in (((512, 512, 256), (5, 5, 5)), ((256, 256, 256), (5, 5, 5)), ((512, 512, 256), (8, 8, 8))):
+        field_bytes = 12 * dims[0] * dims[1] * dims[2]
+        assert bsi.bsi_adjoint_workspace_size(dims, sp) < 0.06 * field_bytes

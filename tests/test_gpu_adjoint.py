@@ -1,0 +1,123 @@
+"""Parity of the HIP adjoint (transpose of Eq. 1) and its autograd wrapper.
+
+Bar: max |gpu - oracle| <= 1e-5 * max|oracle grad| on every control point
+(full FP64 oracle, including the 256^3 workload), the dot-product identity
+<Bx, y> = <x, B^T y> accumulated in FP64 on the host, central finite
+differences on the 12^3 case, bit-identical reruns."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2004_05962_amd as bsi
+import workloads
+from gpu_util import dev, host, max_abs, say
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ((64, 64, 64), (5, 5, 5)),
+    ((1, 1, 1), (1, 1, 1)),
+    ((3, 2, 5), (64, 64, 64)),
+    ((7, 3, 2), (2, 3, 1)),
+    ((130, 9, 11), (5, 4, 3)),
+    ((65, 70, 33), (64, 7, 10)),
+    ((200, 5, 6), (1, 1, 1)),
+    ((33, 40, 129), (8, 33, 6)),      # y spacing above the 32-row brick: unaligned bricks
+    ((96, 80, 72), (3, 5, 8)),
+    ((61, 47, 53), (2, 2, 2)),
+]
+
+
+@pytest.mark.parametrize("dims,spacing", CASES)
+def test_adjoint_matches_oracle(dims, spacing):
+    say("adjoint", dims, spacing)
+    dfield = workloads.random_field(dims, 1.0, seed=200 + sum(dims) + 3 * sum(spacing))
+    got = host(bsi.adjoint(dev(dfield), dims, spacing))
+    ref = oracle.adjoint(dfield, dims, spacing)
+    assert got.shape == ref.shape
+    assert max_abs(got, ref) <= 1e-5 * float(np.abs(ref).max())
+
+
+@pytest.fixture(scope="module")
+def cfg3():
+    return workloads.cfg3()
+
+
+def test_adjoint_256_full_oracle(cfg3):
+    dims, spacing = cfg3["dims"], cfg3["spacing"]
+    say("adjoint 256^3 delta 5 full oracle")
+    d = dev(cfg3["dfield"])
+    got = host(bsi.adjoint(d, dims, spacing))
+    ref = oracle.adjoint(cfg3["dfield"], dims, spacing)
+    err = max_abs(got, ref)
+    assert err <= 1e-5 * float(np.abs(ref).max()), err
+    again = host(bsi.adjoint(d, dims, spacing))
+    assert np.array_equal(got, again)
+
+
+def test_dot_product_identity_256(cfg3):
+    dims, spacing = cfg3["dims"], cfg3["spacing"]
+    say("dot product 256^3")
+    x, y = dev(cfg3["grid"]), dev(cfg3["dfield"])
+    Bx = bsi.forward(x, dims, spacing)
+    BTy = bsi.adjoint(y, dims, spacing)
+    torch.cuda.synchronize()
+    lhs_terms = (Bx.double() * y.double())
+    lhs = lhs_terms.sum().item()
+    rhs = (x.double() * BTy.double()).sum().item()
+    bound = 1e-5 * lhs_terms.abs().sum().item()
+    assert abs(lhs - rhs) <= bound, (lhs, rhs, bound)
+
+
+def test_finite_differences_12():
+    case = workloads.cfg3_fd()
+    dims, spacing = case["dims"], case["spacing"]
+    say("finite differences 12^3")
+    y = dev(case["dfield"])
+    phi = dev(case["grid"])
+    g = host(bsi.adjoint(y, dims, spacing))
+    # FP64 oracle gradient of the same linear functional
+    ref = oracle.adjoint(case["dfield"], dims, spacing)
+    assert max_abs(g, ref) <= 1e-5 * float(np.abs(ref).max())
+    # central differences through the GPU forward: L is linear, so FD is exact
+    # up to FP32 rounding of L
+    eps = 1e-2
+    flat = phi.view(-1)
+    idx = np.random.default_rng(3).choice(flat.numel(), 96, replace=False)
+    L = lambda p: (bsi.forward(p.view(phi.shape), dims, spacing).double() * y.double()).sum().item()
+    gflat = g.reshape(-1)
+    for i in idx:
+        p = flat.clone()
+        m = flat.clone()
+        p[i] += eps
+        m[i] -= eps
+        fd = (L(p) - L(m)) / (2 * eps)
+        assert abs(fd - gflat[i]) <= 1e-3 * max(1.0, abs(gflat[i])), (i, fd, gflat[i])
+
+
+def test_autograd_function():
+    dims, spacing = (50, 37, 29), (5, 4, 3)
+    say("autograd", dims, spacing)
+    grid = dev(workloads.random_grid(dims, spacing, 2.0, seed=9)).requires_grad_(True)
+    w = dev(workloads.random_field(dims, 1.0, seed=10))
+    field = bsi.bsi(grid, dims, spacing)
+    (field * w).sum().backward()
+    expect = bsi.adjoint(w, dims, spacing)
+    torch.cuda.synchronize()
+    assert torch.equal(grid.grad, expect)
+    # autograd accumulates across backward passes; the library overwrites
+    field = bsi.bsi(grid, dims, spacing)
+    (field * w).sum().backward()
+    torch.cuda.synchronize()
+    assert torch.allclose(grid.grad, 2 * expect, rtol=0, atol=0)
+
+
+def test_workspace_too_small_raises():
+    dims, spacing = (40, 30, 20), (5, 5, 5)
+    say("adjoint workspace check")
+    d = torch.zeros(bsi.field_shape(dims), device="cuda")
+    out = torch.empty(bsi.grid_shape(dims, spacing), device="cuda")
+    ws = torch.empty(bsi.bsi_adjoint_workspace_size(dims, spacing) - 4, dtype=torch.uint8, device="cuda")
+    with pytest.raises(bsi.BSIError):
+        bsi.bsi_adjoint(d, dims, spacing, out, ws)

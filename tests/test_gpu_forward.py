@@ -1,0 +1,109 @@
+"""Parity of the HIP forward BSI (Eq. 1) against the FP64 oracle.
+
+Bar: max |gpu - oracle| <= 1e-5 * max|grid| (FP32 against FP64), on every voxel
+for volumes the oracle finishes in seconds (several tiles, ragged tails, odd
+spacings), and on sampled voxels plus size-independent properties at the
+512 x 512 x 256 sizes the benchmark times.  Reruns are bit-identical."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2004_05962_amd as bsi
+import workloads
+from gpu_util import dev, host, max_abs, say
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    ((64, 64, 64), (5, 5, 5)),        # workload 1
+    ((1, 1, 1), (1, 1, 1)),
+    ((1, 1, 1), (64, 64, 64)),
+    ((7, 3, 2), (2, 3, 1)),
+    ((130, 9, 11), (5, 4, 3)),        # x beyond one 64-lane strip, ragged tiles
+    ((65, 70, 33), (64, 7, 10)),      # largest spacing on x
+    ((200, 5, 6), (1, 1, 1)),
+    ((33, 17, 129), (8, 3, 6)),
+    ((96, 80, 72), (3, 5, 8)),
+]
+
+
+def _tol(grid):
+    return 1e-5 * float(np.abs(grid).max())
+
+
+@pytest.mark.parametrize("dims,spacing", CASES)
+def test_forward_matches_oracle(dims, spacing):
+    say("forward", dims, spacing)
+    grid = workloads.random_grid(dims, spacing, 2.0, seed=100 + sum(dims) + 7 * sum(spacing))
+    if dims == (64, 64, 64):
+        grid = workloads.cfg1()["grid"]
+    got = host(bsi.forward(dev(grid), dims, spacing))
+    ref = oracle.forward(grid, dims, spacing)
+    assert got.shape == ref.shape
+    assert max_abs(got, ref) <= _tol(grid)
+
+
+def test_forward_canary_and_rerun_bits():
+    dims, spacing = (77, 45, 31), (5, 4, 6)
+    say("forward canary", dims, spacing)
+    grid = dev(workloads.random_grid(dims, spacing, 2.0, seed=5))
+    n = int(np.prod(bsi.field_shape(dims)))
+    buf = torch.full((n + 4096,), 1.0e30, dtype=torch.float32, device="cuda")
+    field = buf[:n].view(bsi.field_shape(dims))
+    bsi.forward(grid, dims, spacing, out=field)
+    again = bsi.forward(grid, dims, spacing)
+    torch.cuda.synchronize()
+    assert torch.all(buf[n:] == 1.0e30), "kernel wrote past the field"
+    assert not torch.any(field == 1.0e30), "kernel left voxels unwritten"
+    assert torch.equal(field, again)
+
+
+@pytest.mark.parametrize("delta", workloads.CFG2_SPACINGS)
+def test_forward_clinical_size_sampled(delta):
+    case = workloads.cfg2(delta)
+    dims, spacing, grid = case["dims"], case["spacing"], case["grid"]
+    say("forward 512x512x256 delta", delta)
+    g = dev(grid)
+    field = bsi.forward(g, dims, spacing)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(delta)
+    pts = np.stack([rng.integers(0, n, 3000) for n in dims], axis=1)
+    corners = np.array([[x, y, z] for x in (0, dims[0] - 1) for y in (0, dims[1] - 1) for z in (0, dims[2] - 1)])
+    pts = np.concatenate([pts, corners])
+    idx = torch.from_numpy(pts).cuda()
+    got = field[idx[:, 2], idx[:, 1], idx[:, 0]].cpu().numpy()
+    ref = oracle.forward_points(grid, dims, spacing, pts)
+    assert max_abs(got, ref) <= _tol(grid)
+    assert bool(torch.isfinite(field).all())
+    again = bsi.forward(g, dims, spacing)
+    assert torch.equal(field, again)
+
+
+def test_linear_grid_reproduced_at_full_size():
+    # Property at any size: a grid sampled from a linear function of position
+    # (control point a at voxel (a-1)*d) gives that linear function exactly.
+    dims, spacing = workloads.CFG2_DIMS, (5, 5, 5)
+    say("forward linear reproduction 512x512x256")
+    gz, gy, gx, _ = bsi.grid_shape(dims, spacing)
+    Z, Y, X = torch.meshgrid(*[(torch.arange(n, dtype=torch.float64, device="cuda") - 1) * 5 for n in (gz, gy, gx)],
+                             indexing="ij")
+    grid = torch.stack([0.01 * X + 0.5, -0.02 * Y + 0.003 * Z, 0.004 * X + 0.002 * Y - 0.001 * Z], -1).float()
+    field = bsi.forward(grid.contiguous(), dims, spacing)
+    z, y, x = torch.meshgrid(*[torch.arange(n, dtype=torch.float64, device="cuda") for n in (dims[2], dims[1], dims[0])],
+                             indexing="ij")
+    expect = torch.stack([0.01 * x + 0.5, -0.02 * y + 0.003 * z, 0.004 * x + 0.002 * y - 0.001 * z], -1)
+    err = (field.double() - expect).abs().max().item()
+    assert err <= 1e-5 * grid.abs().max().item()
+
+
+def test_rejects_bad_tensors():
+    say("forward argument checks")
+    dims, spacing = (10, 10, 10), (5, 5, 5)
+    g = torch.zeros(bsi.grid_shape(dims, spacing), device="cuda")
+    with pytest.raises(ValueError):
+        bsi.forward(g[:, :, :-1], dims, spacing)
+    with pytest.raises(TypeError):
+        bsi.forward(g.double(), dims, spacing)
+    with pytest.raises(ValueError):
+        bsi.forward(g.cpu(), dims, spacing)
