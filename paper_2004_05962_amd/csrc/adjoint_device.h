@@ -21,13 +21,24 @@
 
 namespace bsi {
 
-constexpr int kAdjWaves = 8;
-constexpr int kAdjThreads = kWave * kAdjWaves;   // 512
-constexpr int kAdjRows = 4;                      // rows per thread
+// Workgroup shape of pass 1 (compile-time; the brick is always at most 64 x 32
+// voxels in x, y, so these knobs change scheduling, never the summation order).
+#ifndef BSI_ADJ_WAVES
+#define BSI_ADJ_WAVES 8
+#endif
+#ifndef BSI_ADJ_PREFETCH
+#define BSI_ADJ_PREFETCH 2
+#endif
+constexpr int kAdjWaves = BSI_ADJ_WAVES;
+constexpr int kAdjThreads = kWave * kAdjWaves;
 constexpr int kAdjMaxX = kWave;                  // 64
-constexpr int kAdjMaxY = kAdjWaves * kAdjRows;   // 32
+constexpr int kAdjMaxY = 32;
+constexpr int kAdjRows = kAdjMaxY / kAdjWaves;   // rows per thread
+constexpr int kAdjPrefetch = BSI_ADJ_PREFETCH;   // z-planes loaded ahead
 constexpr int kAdjMaxCx = (kAdjMaxX - 1) + 5;    // window bound at spacing 1
 constexpr int kAdjTargetZ = 24;
+static_assert(kAdjRows * kAdjWaves == kAdjMaxY, "rows must tile the 32-row brick");
+static_assert(kAdjPrefetch >= 1 && kAdjPrefetch <= 4, "prefetch depth 1..4");
 
 struct AdjSmem {
   float V[kAdjMaxY * kAdjMaxX * 3];    // finished plane A(x, y), per component
@@ -80,43 +91,59 @@ __device__ __forceinline__ void adj_emit(const AdjGeom& a, const AdjBrick& b, fl
   }
   __syncthreads();
 
+  // x-contraction: one item per (row, cx), all three components
   const int txlo = b.x0 / g.dx, txhi = (b.xe - 1) / g.dx;
-  const int n1 = (b.ye - b.y0) * b.Cx * 3;
+  const int n1 = (b.ye - b.y0) * b.Cx;
   for (int it = tid; it < n1; it += kAdjThreads) {
-    const int c = it % 3;
-    const int r = it / 3;
-    const int cxl = r % b.Cx;
-    const int yl = r / b.Cx;
+    const int yl = it / b.Cx;
+    const int cxl = it - yl * b.Cx;
     const int cx = b.cx0 + cxl;
-    float s = 0.f;
+    const float* vrow = sm.V + yl * kAdjMaxX * 3;
+    float sx = 0.f, sy = 0.f, sz = 0.f;
     for (int l = 0; l < 4; ++l) {
       const int tile = cx - l;
       if (tile < txlo || tile > txhi) continue;
       const int xa = max(tile * g.dx, b.x0) - b.x0;
       const int xb = min(tile * g.dx + g.dx, b.xe) - b.x0;
-      for (int xl = xa; xl < xb; ++xl) s = fmaf(sm.WX[xl * 4 + l], sm.V[(yl * kAdjMaxX + xl) * 3 + c], s);
+#pragma unroll 4
+      for (int xl = xa; xl < xb; ++xl) {
+        const float wv = sm.WX[xl * 4 + l];
+        const float* v = vrow + xl * 3;
+        sx = fmaf(wv, v[0], sx);
+        sy = fmaf(wv, v[1], sy);
+        sz = fmaf(wv, v[2], sz);
+      }
     }
-    sm.Sx[(yl * kAdjMaxCx + cxl) * 3 + c] = s;
+    float* o = sm.Sx + (yl * kAdjMaxCx + cxl) * 3;
+    o[0] = sx;
+    o[1] = sy;
+    o[2] = sz;
   }
   __syncthreads();
 
+  // y-contraction: one item per (cy, cx), all three components
   const int tylo = b.y0 / g.dy, tyhi = (b.ye - 1) / g.dy;
-  const int n2 = b.Cy * b.Cx * 3;
+  const int n2 = b.Cy * b.Cx;
   for (int it = tid; it < n2; it += kAdjThreads) {
-    const int c = it % 3;
-    const int r = it / 3;
-    const int cxl = r % b.Cx;
-    const int cyl = r / b.Cx;
+    const int cyl = it / b.Cx;
+    const int cxl = it - cyl * b.Cx;
     const int cy = b.cy0 + cyl;
-    float s = 0.f;
+    float sx = 0.f, sy = 0.f, sz = 0.f;
     for (int m = 0; m < 4; ++m) {
       const int tile = cy - m;
       if (tile < tylo || tile > tyhi) continue;
       const int ya = max(tile * g.dy, b.y0) - b.y0;
       const int yb = min(tile * g.dy + g.dy, b.ye) - b.y0;
-      for (int yl = ya; yl < yb; ++yl) s = fmaf(sm.WY[yl * 4 + m], sm.Sx[(yl * kAdjMaxCx + cxl) * 3 + c], s);
+#pragma unroll 4
+      for (int yl = ya; yl < yb; ++yl) {
+        const float wv = sm.WY[yl * 4 + m];
+        const float* v = sm.Sx + (yl * kAdjMaxCx + cxl) * 3;
+        sx = fmaf(wv, v[0], sx);
+        sy = fmaf(wv, v[1], sy);
+        sz = fmaf(wv, v[2], sz);
+      }
     }
-    pbase[((size_t)(czl * a.cym + cyl) * a.cxm + cxl) * 3 + c] = s;
+    stf3(pbase + ((size_t)(czl * a.cym + cyl) * a.cxm + cxl) * 3, F3{sx, sy, sz});
   }
   // No trailing barrier: the next emit's first barrier orders these LDS reads
   // before its Sx writes, and its V writes come after this emit's second barrier.
@@ -170,12 +197,13 @@ __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, floa
     for (int n = 0; n < 4; ++n) acc[k][n] = F3{0.f, 0.f, 0.f};
 
   const F3 zero{0.f, 0.f, 0.f};
-  F3 p0[kAdjRows], p1[kAdjRows];
+  // ring of the next kAdjPrefetch z-planes of every row (registers)
+  F3 pf[kAdjPrefetch][kAdjRows];
 #pragma unroll
-  for (int k = 0; k < kAdjRows; ++k) {
-    p0[k] = act[k] ? ldf3(src[k]) : zero;
-    p1[k] = (act[k] && b.z0 + 1 < b.ze) ? ldf3(src[k] + zs) : zero;
-  }
+  for (int j = 0; j < kAdjPrefetch; ++j)
+#pragma unroll
+    for (int k = 0; k < kAdjRows; ++k)
+      pf[j][k] = (act[k] && b.z0 + j < b.ze) ? ldf3(src[k] + (size_t)j * zs) : zero;
 
   int tz = b.cz0;
   int oz = b.z0 - tz * g.dz;
@@ -183,9 +211,11 @@ __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, floa
     F3 cur[kAdjRows];
 #pragma unroll
     for (int k = 0; k < kAdjRows; ++k) {
-      cur[k] = p0[k];
-      p0[k] = p1[k];
-      p1[k] = (act[k] && z + 2 < b.ze) ? ldf3(src[k] + (size_t)(z + 2 - b.z0) * zs) : zero;
+      cur[k] = pf[0][k];
+#pragma unroll
+      for (int j = 0; j + 1 < kAdjPrefetch; ++j) pf[j][k] = pf[j + 1][k];
+      const int zn = z + kAdjPrefetch;
+      pf[kAdjPrefetch - 1][k] = (act[k] && zn < b.ze) ? ldf3(src[k] + (size_t)(zn - b.z0) * zs) : zero;
     }
     const float* wz = lut_row(lut, g.dz, oz);
     const float w0 = wz[0], w1 = wz[1], w2 = wz[2], w3 = wz[3];

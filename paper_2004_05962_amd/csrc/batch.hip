@@ -87,12 +87,11 @@ __device__ __forceinline__ Slice make_slice(int64_t total, int chunked) {
   return s;
 }
 
-__global__ __launch_bounds__(kWave* kFwdRows) void batch_fwd_kernel(const VolDesc* __restrict__ vols, int count,
-                                                                     int64_t total, int chunked,
-                                                                     const float* __restrict__ lut) {
+__global__ __launch_bounds__(kFwdThreads) void batch_fwd_kernel(const VolDesc* __restrict__ vols, int count,
+                                                                 int64_t total, int chunked,
+                                                                 const float* __restrict__ lut) {
+  __shared__ FwdSmem sm;
   const Slice s = make_slice(total, chunked);
-  const int wave = uniform(threadIdx.x / kWave);
-  const int lane = threadIdx.x & (kWave - 1);
   for (int64_t item = s.begin; item < s.end; item += s.step) {
     const int vi = uniform(find_volume(vols, count, item, kFwd));
     const VolDesc& d = vols[vi];
@@ -103,12 +102,9 @@ __global__ __launch_bounds__(kWave* kFwdRows) void batch_fwd_kernel(const VolDes
     id /= L.nbx;
     const int by = id % L.nby;
     const int bz = id / L.nby;
-    const int y = by * kFwdRows + wave;
-    if (y < g.ny) {
-      const int z0 = bz * L.zchunk;
-      const int z1 = min(g.nz, z0 + L.zchunk);
-      fwd_wave(d.grid, d.field, g, lut, bx * kWave, y, z0, z1, lane);
-    }
+    const int z0 = bz * L.zchunk;
+    const int z1 = min(g.nz, z0 + L.zchunk);
+    fwd_block(d.grid, d.field, g, lut, bx * kWave, by * kFwdRows, z0, z1, sm, threadIdx.x);
   }
 }
 
@@ -196,7 +192,7 @@ hipError_t launch_pass(bsi_batch* p, int pass, hipStream_t s) {
   if (grid > 0x7fffffff) grid = 0x7fffffff;
   const int chunked = per_cu == 0 ? 0 : sc.chunked;
   if (pass == kFwd)
-    hipLaunchKernelGGL(batch_fwd_kernel, dim3((unsigned)grid), dim3(kWave * kFwdRows), 0, s, p->d_desc,
+    hipLaunchKernelGGL(batch_fwd_kernel, dim3((unsigned)grid), dim3(kFwdThreads), 0, s, p->d_desc,
                        p->count, total, chunked, p->lut);
   else if (pass == kAdj1)
     hipLaunchKernelGGL(batch_adj1_kernel, dim3((unsigned)grid), dim3(kAdjThreads), 0, s, p->d_desc, p->count,

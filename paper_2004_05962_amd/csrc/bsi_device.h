@@ -56,9 +56,25 @@ __device__ __forceinline__ int xcd_remap(int id, int n) {
 __device__ __forceinline__ F3 ldf3(const float* p) { return *reinterpret_cast<const F3*>(p); }
 __device__ __forceinline__ void stf3(float* p, F3 v) { *reinterpret_cast<F3*>(p) = v; }
 
+// Streaming store of the dense field: non-temporal, so the write stream does not
+// evict the control points that neighbouring waves still read from L2.
+#ifndef BSI_FWD_NT
+#define BSI_FWD_NT 1
+#endif
+__device__ __forceinline__ void stf3_stream(float* p, F3 v) {
+#if BSI_FWD_NT
+  __builtin_nontemporal_store(v.x, p);
+  __builtin_nontemporal_store(v.y, p + 1);
+  __builtin_nontemporal_store(v.z, p + 2);
+#else
+  stf3(p, v);
+#endif
+}
+
 // ----------------------------------------------------------------------------
-// Forward BSI for one wave: 64 consecutive voxels x0..x0+63 of row y, planes
-// z0..z1-1 (x0, y, z0, z1 wave-uniform).
+// Forward BSI for one workgroup: kFwdRows consecutive rows y0.. of the 64-voxel
+// x-strip x0..x0+63 (lane = x), voxel planes z0..z1-1.  All bounds are
+// workgroup-uniform.
 //
 // Sum factorisation of Eq. 1, per lane: for control plane cz,
 //   Q(cz) = sum_m By_m(v) * (sum_l Bx_l(u) * phi[cz][ty+m][tx+l])
@@ -66,75 +82,146 @@ __device__ __forceinline__ void stf3(float* p, F3 v) { *reinterpret_cast<F3*>(p)
 //   T = sum_n Bz_n(w) * Q(tz+n).
 // Q is kept for a rolling window of 4 planes in registers, so each control
 // plane is contracted once per row and reused by the dz voxel planes of each of
-// the 4 tiles that read it.  The raw control points of the next plane are
-// prefetched while the current tile is written.  Each voxel is one 12-byte
-// store, so a wave writes 768 contiguous bytes per plane.
+// the 4 tiles that read it.  The control points the workgroup needs from a plane
+// (a window of at most kFwdMaxCy x kFwdMaxCx points) are staged once in a
+// two-slot LDS ring: the next plane is loaded into registers (a few floats per
+// thread, coalesced rows) while the current tile is written, then stored to the
+// free slot; one barrier per tile.  Each voxel is one 12-byte store, so a wave
+// writes 768 contiguous bytes per plane.
 // ----------------------------------------------------------------------------
-__device__ __forceinline__ F3 fwd_contract(const F3 (&r)[16], float bx0, float bx1, float bx2,
-                                           float bx3, float by0, float by1, float by2, float by3) {
-  F3 row[4];
+#ifndef BSI_FWD_ROWS
+#define BSI_FWD_ROWS 4
+#endif
+constexpr int kFwdRows = BSI_FWD_ROWS;                 // waves (rows) per workgroup
+constexpr int kFwdThreads = kWave * kFwdRows;
+constexpr int kFwdMaxCx = (kWave - 1) + 4;             // window width at spacing 1
+constexpr int kFwdMaxCy = (kFwdRows - 1) + 4;          // window height at spacing 1
+constexpr int kFwdPitch = kFwdMaxCx * 3;               // floats per staged control row
+constexpr int kFwdPlane = kFwdMaxCy * kFwdPitch;       // floats per staged plane
+constexpr int kFwdLoads = (kFwdPlane + kFwdThreads - 1) / kFwdThreads;
+
+struct FwdSmem {
+  float ring[2][kFwdLoads * kFwdThreads];
+};
+
+// Staging map: thread tid moves floats e = tid + k * kFwdThreads of the window,
+// e = row * kFwdPitch + col; goff[k] is its grid offset within a plane, or -1
+// when e lies outside this workgroup's window.
+struct FwdStage {
+  int goff[kFwdLoads];
+};
+
+__device__ __forceinline__ FwdStage fwd_stage_map(const VolGeom& g, int cx0, int ncx, int cy0, int ncy, int tid) {
+  FwdStage m;
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const F3 a = r[4 * m], b = r[4 * m + 1], c = r[4 * m + 2], d = r[4 * m + 3];
-    row[m].x = fmaf(bx3, d.x, fmaf(bx2, c.x, fmaf(bx1, b.x, bx0 * a.x)));
-    row[m].y = fmaf(bx3, d.y, fmaf(bx2, c.y, fmaf(bx1, b.y, bx0 * a.y)));
-    row[m].z = fmaf(bx3, d.z, fmaf(bx2, c.z, fmaf(bx1, b.z, bx0 * a.z)));
+  for (int k = 0; k < kFwdLoads; ++k) {
+    const int e = tid + k * kFwdThreads;
+    const int row = e / kFwdPitch;
+    const int col = e - row * kFwdPitch;
+    m.goff[k] = (row < ncy && col < ncx * 3) ? ((cy0 + row) * g.gx + cx0) * 3 + col : -1;
   }
-  F3 q;
-  q.x = fmaf(by3, row[3].x, fmaf(by2, row[2].x, fmaf(by1, row[1].x, by0 * row[0].x)));
-  q.y = fmaf(by3, row[3].y, fmaf(by2, row[2].y, fmaf(by1, row[1].y, by0 * row[0].y)));
-  q.z = fmaf(by3, row[3].z, fmaf(by2, row[2].z, fmaf(by1, row[1].z, by0 * row[0].z)));
+  return m;
+}
+
+__device__ __forceinline__ void fwd_fetch(const float* __restrict__ grid, const VolGeom& g, const FwdStage& m,
+                                          int cz, float (&r)[kFwdLoads]) {
+  const float* plane = grid + (size_t)cz * g.gy * g.gx * 3;
+#pragma unroll
+  for (int k = 0; k < kFwdLoads; ++k) r[k] = m.goff[k] >= 0 ? plane[m.goff[k]] : 0.f;
+}
+
+__device__ __forceinline__ void fwd_stage(float* __restrict__ slot, int tid, const float (&r)[kFwdLoads]) {
+#pragma unroll
+  for (int k = 0; k < kFwdLoads; ++k) slot[tid + k * kFwdThreads] = r[k];
+}
+
+// Q for this lane's (x, y) from a staged plane: the x-contraction of each of the
+// 4 control rows, then the y-contraction with weights wy[0..3].  The row loop is
+// kept rolled so only one row (12 values) is in flight: a small register
+// footprint, i.e. more waves per SIMD to hide LDS and memory latency.
+__device__ __forceinline__ F3 fwd_contract(const float* __restrict__ slot, int base, float bx0, float bx1,
+                                           float bx2, float bx3, const float* __restrict__ wy) {
+  F3 q{0.f, 0.f, 0.f};
+#pragma unroll 1
+  for (int m = 0; m < 4; ++m) {
+    const float* p = slot + base + m * kFwdPitch;
+    const float rx = fmaf(bx3, p[9], fmaf(bx2, p[6], fmaf(bx1, p[3], bx0 * p[0])));
+    const float ry = fmaf(bx3, p[10], fmaf(bx2, p[7], fmaf(bx1, p[4], bx0 * p[1])));
+    const float rz = fmaf(bx3, p[11], fmaf(bx2, p[8], fmaf(bx1, p[5], bx0 * p[2])));
+    const float b = wy[m];
+    if (m == 0) {
+      q.x = b * rx;
+      q.y = b * ry;
+      q.z = b * rz;
+    } else {
+      q.x = fmaf(b, rx, q.x);
+      q.y = fmaf(b, ry, q.y);
+      q.z = fmaf(b, rz, q.z);
+    }
+  }
   return q;
 }
 
-__device__ __forceinline__ void fwd_load_plane(const float* __restrict__ base, size_t row_stride,
-                                               F3 (&r)[16]) {
-#pragma unroll
-  for (int m = 0; m < 4; ++m)
-#pragma unroll
-    for (int l = 0; l < 4; ++l) r[4 * m + l] = ldf3(base + m * row_stride + 3 * l);
-}
+// Collective over the workgroup (kFwdThreads threads, all bounds uniform).
+__device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float* __restrict__ field,
+                                          const VolGeom& g, const float* __restrict__ lut, int x0, int y0,
+                                          int z0, int z1, FwdSmem& sm, int tid) {
+  const int lane = tid & (kWave - 1);
+  const int wave = uniform(tid / kWave);
+  const int cx0 = x0 / g.dx;
+  const int ncx = (min(x0 + kWave, g.nx) - 1) / g.dx - cx0 + 4;
+  const int cy0 = y0 / g.dy;
+  const int ncy = (min(y0 + kFwdRows, g.ny) - 1) / g.dy - cy0 + 4;
+  const FwdStage map = fwd_stage_map(g, cx0, ncx, cy0, ncy, tid);
 
-__device__ __forceinline__ void fwd_wave(const float* __restrict__ grid, float* __restrict__ field,
-                                         const VolGeom& g, const float* __restrict__ lut, int x0,
-                                         int y, int z0, int z1, int lane) {
   const int x = x0 + lane;
-  const bool active = x < g.nx;
-  const int xc = active ? x : g.nx - 1;  // idle lanes read a valid column, store nothing
+  const int y = y0 + wave;
+  const bool active = x < g.nx && y < g.ny;
+  const int xc = min(x, g.nx - 1);  // idle lanes read a valid column, store nothing
+  const int yc = min(y, g.ny - 1);
   const int tx = xc / g.dx;
   const int ox = xc - tx * g.dx;
+  const int ty = yc / g.dy;
+  const int oy = yc - ty * g.dy;
   const float* wx = lut_row(lut, g.dx, ox);
   const float bx0 = wx[0], bx1 = wx[1], bx2 = wx[2], bx3 = wx[3];
-  const int ty = y / g.dy;
-  const int oy = y - ty * g.dy;
-  const float* wy = lut_row(lut, g.dy, oy);
-  const float by0 = wy[0], by1 = wy[1], by2 = wy[2], by3 = wy[3];
-
-  const size_t row_stride = (size_t)g.gx * 3;
-  const size_t plane_stride = (size_t)g.gy * row_stride;
-  const float* gbase = grid + (size_t)ty * row_stride + (size_t)tx * 3;
+  const float* wy = lut_row(lut, g.dy, oy);  // wave-uniform
+  const int base = (ty - cy0) * kFwdPitch + (tx - cx0) * 3;
 
   int tz = z0 / g.dz;
   int oz = z0 - tz * g.dz;
-  F3 raw[16];
-  fwd_load_plane(gbase + (size_t)tz * plane_stride, row_stride, raw);
-  F3 q0 = fwd_contract(raw, bx0, bx1, bx2, bx3, by0, by1, by2, by3);
-  fwd_load_plane(gbase + (size_t)(tz + 1) * plane_stride, row_stride, raw);
-  F3 q1 = fwd_contract(raw, bx0, bx1, bx2, bx3, by0, by1, by2, by3);
-  fwd_load_plane(gbase + (size_t)(tz + 2) * plane_stride, row_stride, raw);
-  F3 q2 = fwd_contract(raw, bx0, bx1, bx2, bx3, by0, by1, by2, by3);
-  fwd_load_plane(gbase + (size_t)(tz + 3) * plane_stride, row_stride, raw);
+  float r[kFwdLoads];
+  // Warm-up: stage planes tz, tz+1, tz+2 one at a time (slots 0, 1, 0) and shift
+  // their contractions into q0..q2; then stage plane tz+3 into slot 1 (its
+  // contraction is the loop head).  One plane in flight keeps registers low.
+  F3 q0{0.f, 0.f, 0.f}, q1{0.f, 0.f, 0.f}, q2{0.f, 0.f, 0.f};
+#pragma unroll 1
+  for (int j = 0; j < 3; ++j) {
+    __syncthreads();  // the slot may still be read (previous item or iteration)
+    fwd_fetch(grid, g, map, tz + j, r);
+    fwd_stage(sm.ring[j & 1], tid, r);
+    __syncthreads();
+    const F3 qn = fwd_contract(sm.ring[j & 1], base, bx0, bx1, bx2, bx3, wy);
+    q0 = q1;
+    q1 = q2;
+    q2 = qn;
+  }
+  __syncthreads();
+  fwd_fetch(grid, g, map, tz + 3, r);
+  fwd_stage(sm.ring[1], tid, r);
+  __syncthreads();
+  int slot3 = 1;  // slot holding plane tz + 3
 
   const size_t zstride = (size_t)g.ny * g.nx * 3;
-  float* out = field + (((size_t)z0 * g.ny + y) * g.nx + x) * 3;
+  float* out = field + (((size_t)z0 * g.ny + yc) * g.nx + xc) * 3;
   int z = z0;
   for (;;) {
-    const F3 q3 = fwd_contract(raw, bx0, bx1, bx2, bx3, by0, by1, by2, by3);
+    const F3 q3 = fwd_contract(sm.ring[slot3], base, bx0, bx1, bx2, bx3, wy);
     const int left = z1 - z;
-    const int oend = (g.dz - oz < left) ? g.dz : oz + left;
-    // Another tile follows inside this range: prefetch its new plane (tz + 4 is
-    // then at most ceil(nz/dz) + 2 = gz - 1, in bounds).
-    if (g.dz - oz < left) fwd_load_plane(gbase + (size_t)(tz + 4) * plane_stride, row_stride, raw);
+    const bool more = g.dz - oz < left;  // another tile follows inside this range
+    // its new plane tz + 4 is then at most ceil(nz/dz) + 2 = gz - 1: in bounds
+    if (more) fwd_fetch(grid, g, map, tz + 4, r);
+    const int oend = more ? g.dz : oz + left;
     for (; oz < oend; ++oz, ++z) {
       const float* wz = lut_row(lut, g.dz, oz);
       const float w0 = wz[0], w1 = wz[1], w2 = wz[2], w3 = wz[3];
@@ -142,10 +229,14 @@ __device__ __forceinline__ void fwd_wave(const float* __restrict__ grid, float* 
       t.x = fmaf(w3, q3.x, fmaf(w2, q2.x, fmaf(w1, q1.x, w0 * q0.x)));
       t.y = fmaf(w3, q3.y, fmaf(w2, q2.y, fmaf(w1, q1.y, w0 * q0.y)));
       t.z = fmaf(w3, q3.z, fmaf(w2, q2.z, fmaf(w1, q1.z, w0 * q0.z)));
-      if (active) stf3(out, t);
+      if (active) stf3_stream(out, t);
       out += zstride;
     }
-    if (z >= z1) break;
+    if (!more) break;
+    // plane tz + 4 goes to the slot of plane tz + 2, consumed one tile ago
+    fwd_stage(sm.ring[slot3 ^ 1], tid, r);
+    __syncthreads();
+    slot3 ^= 1;
     oz = 0;
     ++tz;
     q0 = q1;

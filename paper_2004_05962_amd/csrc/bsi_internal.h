@@ -31,7 +31,10 @@ size_t adj_workspace_bytes(const AdjGeom& a);
 struct FwdLaunch {
   int nbx, nby, nbz, zchunk;
 };
-constexpr int kFwdRows = 4;
+#ifndef BSI_FWD_BLOCKS
+#define BSI_FWD_BLOCKS 2048
+#endif
+constexpr int kFwdTargetBlocks = BSI_FWD_BLOCKS; // z is split until this many workgroups
 FwdLaunch make_fwd_launch(const VolGeom& g);
 
 hipError_t launch_forward(const float* grid, float* field, const VolGeom& g, const float* lut,

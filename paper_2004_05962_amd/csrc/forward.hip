@@ -1,41 +1,38 @@
 // Forward BSI kernel (Eq. 1) for one volume.
 //
 // Workgroup = kFwdRows waves = kFwdRows consecutive rows of one 64-voxel x-strip,
-// over one chunk of z.  Each wave runs fwd_wave (bsi_device.h): per-lane sum
+// over one chunk of z; it runs fwd_block (bsi_device.h): per-lane sum
 // factorisation with a rolling window of 4 contracted control planes in
-// registers and one coalesced 12-byte store per voxel.  The field write is the
-// dominant HBM traffic (12 bytes per voxel against 12 bytes per control point).
+// registers, control points staged per plane in LDS, and one coalesced 12-byte
+// store per voxel.  The field write is the dominant HBM traffic (12 bytes per
+// voxel against 12 bytes per control point).
 #include "bsi_internal.h"
 
 namespace bsi {
 
-__global__ __launch_bounds__(kWave* kFwdRows) void fwd_kernel(const float* __restrict__ grid,
-                                                               float* __restrict__ field, VolGeom g,
-                                                               const float* __restrict__ lut,
-                                                               FwdLaunch L) {
+__global__ __launch_bounds__(kFwdThreads) void fwd_kernel(const float* __restrict__ grid,
+                                                           float* __restrict__ field, VolGeom g,
+                                                           const float* __restrict__ lut, FwdLaunch L) {
+  __shared__ FwdSmem sm;
   int id = xcd_remap(blockIdx.x, gridDim.x);
   const int bx = id % L.nbx;
   id /= L.nbx;
   const int by = id % L.nby;
   const int bz = id / L.nby;
-  const int wave = uniform(threadIdx.x / kWave);
-  const int lane = threadIdx.x & (kWave - 1);
-  const int y = by * kFwdRows + wave;
-  if (y >= g.ny) return;  // whole wave idle; no barrier in this kernel
   const int z0 = bz * L.zchunk;
   const int z1 = min(g.nz, z0 + L.zchunk);
-  fwd_wave(grid, field, g, lut, bx * kWave, y, z0, z1, lane);
+  fwd_block(grid, field, g, lut, bx * kWave, by * kFwdRows, z0, z1, sm, threadIdx.x);
 }
 
 FwdLaunch make_fwd_launch(const VolGeom& g) {
   FwdLaunch L;
   L.nbx = (g.nx + kWave - 1) / kWave;
   L.nby = (g.ny + kFwdRows - 1) / kFwdRows;
-  // Split z (at tile boundaries) until there are >= 2048 workgroups
-  // (8 per CU): enough waves to keep the stores flowing.
+  // Split z (at tile boundaries) until there are >= kFwdTargetBlocks
+  // workgroups: enough waves to keep the stores flowing.
   const int tiles_z = (g.nz + g.dz - 1) / g.dz;
   const long base = (long)L.nbx * L.nby;
-  int chunks = (int)((2048 + base - 1) / base);
+  int chunks = (int)((kFwdTargetBlocks + base - 1) / base);
   if (chunks > tiles_z) chunks = tiles_z;
   if (chunks < 1) chunks = 1;
   const int tiles_per_chunk = (tiles_z + chunks - 1) / chunks;
@@ -48,7 +45,7 @@ hipError_t launch_forward(const float* grid, float* field, const VolGeom& g, con
                           hipStream_t s) {
   const FwdLaunch L = make_fwd_launch(g);
   const long blocks = (long)L.nbx * L.nby * L.nbz;
-  hipLaunchKernelGGL(fwd_kernel, dim3((unsigned)blocks), dim3(kWave * kFwdRows), 0, s, grid, field, g,
+  hipLaunchKernelGGL(fwd_kernel, dim3((unsigned)blocks), dim3(kFwdThreads), 0, s, grid, field, g,
                      lut, L);
   return hipGetLastError();
 }
