@@ -113,6 +113,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--quick", action="store_true", help="main step only: no extras, no CPU baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run 3 plain device-to-device copies of 805,306,368 bytes (the known-size "
+                         "reference that rocprofv3 FETCH_SIZE / WRITE_SIZE are scaled by)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the hot path here runs on a single MI355X; "
@@ -177,6 +180,14 @@ def main():
              "adjoint_gvoxel_s": round(V / (adj_ms * 1e-3) / 1e9, 2)}
     log("main:", json.dumps(other))
 
+    if args.copy_calibration:
+        src = torch.ones(805306368 // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     extras = {}
     if not args.quick:
         extras = run_extras(torch, bsi, workloads)
@@ -198,10 +209,13 @@ def main():
 
 def run_extras(torch, bsi, workloads):
     ex = {}
-    flush_buf = torch.empty(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB, > 256 MB MALL
+    # Evict the 256 MB MALL between repetitions by READING 1 GiB: a write-based
+    # flush would leave dirty lines whose write-back lands inside the next
+    # measured kernel.
+    flush_buf = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
 
     def flush():
-        flush_buf.zero_()
+        flush_buf.sum()
 
     # forward at the other clinical spacings
     for d in (3, 8):

@@ -5,14 +5,15 @@
 
 namespace bsi {
 
+template <int DX>
 __global__ __launch_bounds__(kAdjThreads) void adj_pass1_kernel(const float* __restrict__ dfield,
                                                                  float* __restrict__ part, AdjGeom a,
                                                                  const float* __restrict__ lut) {
   __shared__ AdjSmem sm;
-  const int nbricks = a.nbx * a.nby * a.nbz;
+  const int nbricks = a.x.nb * a.y.nb * a.z.nb;
   const int brick = xcd_remap(blockIdx.x, gridDim.x);
   if (brick >= nbricks) return;  // uniform over the workgroup
-  adj_brick(dfield, part, a, lut, brick, sm, threadIdx.x);
+  adj_brick<DX>(dfield, part, a, lut, brick, sm, threadIdx.x);
 }
 
 constexpr int kGatherThreads = 256;
@@ -29,31 +30,72 @@ __global__ __launch_bounds__(kGatherThreads) void adj_pass2_kernel(const float* 
   stf3(grad + i * 3, adj_gather_point(part, a, cx, cy, cz));
 }
 
+namespace {
+AdjAxis make_axis(int n, int d, int u, int nb) {
+  AdjAxis a;
+  a.u = u;
+  a.U = (n + u - 1) / u;
+  a.nb = nb;
+  const int umax = (a.U + nb - 1) / nb;  // units in the largest brick
+  a.cm = (umax * u - 1) / d + 5;
+  return a;
+}
+}  // namespace
+
 AdjGeom make_adj_geom(const VolGeom& g) {
   AdjGeom a;
   a.g = g;
-  // Tile-aligned bricks where the spacing divides into the brick bound.
-  a.xb = g.dx * (kAdjMaxX / g.dx);  // dx <= 64, so >= 1 tile and <= 64 voxels
-  a.yb = g.dy <= kAdjMaxY ? g.dy * (kAdjMaxY / g.dy) : kAdjMaxY;
-  a.zb = g.dz * (kAdjTargetZ / g.dz > 0 ? kAdjTargetZ / g.dz : 1);
-  a.nbx = (g.nx + a.xb - 1) / a.xb;
-  a.nby = (g.ny + a.yb - 1) / a.yb;
-  a.nbz = (g.nz + a.zb - 1) / a.zb;
-  a.cxm = (a.xb - 1) / g.dx + 5;
-  a.cym = (a.yb - 1) / g.dy + 5;
-  a.czm = (a.zb - 1) / g.dz + 5;
+  // x: whole tiles, at most kAdjTilesX per brick
+  const int Ux = (g.nx + g.dx - 1) / g.dx;
+  a.x = make_axis(g.nx, g.dx, g.dx, (Ux + kAdjTilesX - 1) / kAdjTilesX);
+  // y: whole tiles (single rows when a tile is taller than kAdjMaxY), <= kAdjMaxY rows per brick
+  const int uy = g.dy <= kAdjMaxY ? g.dy : 1;
+  const int Uy = (g.ny + uy - 1) / uy;
+  const int my = kAdjMaxY / uy;
+  a.y = make_axis(g.ny, g.dy, uy, (Uy + my - 1) / my);
+  // z: whole tiles; about kAdjTargetZ voxels deep, or the count in
+  // [ceil(Uz/6), ceil(Uz/2)] that best fills whole rounds of kAdjSlots
+  const int Uz = (g.nz + g.dz - 1) / g.dz;
+  const int mz = kAdjTargetZ / g.dz > 0 ? kAdjTargetZ / g.dz : 1;
+  const long base = (long)a.x.nb * a.y.nb;
+  int nbz = (Uz + mz - 1) / mz;
+  const int lo = (Uz + 5) / 6 > 0 ? (Uz + 5) / 6 : 1;
+  const int hi = (Uz + 1) / 2 > 0 ? (Uz + 1) / 2 : 1;
+  if (base * hi >= kAdjSlots) {
+    double best = -1.0;
+    for (int c = lo; c <= hi; ++c) {
+      const long tot = base * c;
+      const long rounds = (tot + kAdjSlots - 1) / kAdjSlots;
+      const double eff = (double)tot / (double)(rounds * kAdjSlots);
+      if (eff > best + 1e-9) {
+        best = eff;
+        nbz = c;
+      }
+    }
+  }
+  a.z = make_axis(g.nz, g.dz, g.dz, nbz);
   return a;
 }
 
 size_t adj_workspace_bytes(const AdjGeom& a) {
-  return (size_t)a.nbx * a.nby * a.nbz * a.czm * a.cym * a.cxm * 3 * sizeof(float);
+  return (size_t)a.x.nb * a.y.nb * a.z.nb * a.x.cm * a.y.cm * a.z.cm * 3 * sizeof(float);
 }
 
 hipError_t launch_adjoint(const float* dfield, float* grad, const AdjGeom& a, const float* lut,
                           float* part, hipStream_t s) {
-  const long nbricks = (long)a.nbx * a.nby * a.nbz;
-  hipLaunchKernelGGL(adj_pass1_kernel, dim3((unsigned)nbricks), dim3(kAdjThreads), 0, s, dfield, part,
-                     a, lut);
+  const long nbricks = (long)a.x.nb * a.y.nb * a.z.nb;
+  const dim3 grid((unsigned)nbricks), block(kAdjThreads);
+  switch (a.g.dx) {
+    case 1: hipLaunchKernelGGL(adj_pass1_kernel<1>, grid, block, 0, s, dfield, part, a, lut); break;
+    case 2: hipLaunchKernelGGL(adj_pass1_kernel<2>, grid, block, 0, s, dfield, part, a, lut); break;
+    case 3: hipLaunchKernelGGL(adj_pass1_kernel<3>, grid, block, 0, s, dfield, part, a, lut); break;
+    case 4: hipLaunchKernelGGL(adj_pass1_kernel<4>, grid, block, 0, s, dfield, part, a, lut); break;
+    case 5: hipLaunchKernelGGL(adj_pass1_kernel<5>, grid, block, 0, s, dfield, part, a, lut); break;
+    case 6: hipLaunchKernelGGL(adj_pass1_kernel<6>, grid, block, 0, s, dfield, part, a, lut); break;
+    case 7: hipLaunchKernelGGL(adj_pass1_kernel<7>, grid, block, 0, s, dfield, part, a, lut); break;
+    case 8: hipLaunchKernelGGL(adj_pass1_kernel<8>, grid, block, 0, s, dfield, part, a, lut); break;
+    default: hipLaunchKernelGGL(adj_pass1_kernel<0>, grid, block, 0, s, dfield, part, a, lut); break;
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const long npts = (long)a.g.gx * a.g.gy * a.g.gz;

@@ -1,117 +1,147 @@
 // Adjoint of Eq. 1 (its transpose), as a deterministic two-pass gather.
 //
-// Pass 1 (one workgroup per brick).  The volume is cut into bricks of
-// xb x yb x zb voxels, aligned to tiles where the spacing allows.  A workgroup
-// reads its brick's dfield exactly once, in coalesced 12-byte-per-lane loads
-// (lane = x, 8 waves x 4 rows = 32 rows), marching along z.  Each column keeps
-// the z-contraction for the 4 control planes its current tile touches,
-//   A[n] += Bz_n(w) * dfield[z][y][x]       (n = cz - tz),
-// and when a tile ends the finished plane is contracted over x and y in LDS:
-//   Sx[y][cx] = sum_l sum_{x in tile cx-l} Bx_l(u(x)) * A(x, y)
+// Pass 1 (one workgroup per brick).  Each axis is cut into whole tiles (rows
+// instead when a y-tile is taller than a brick), spread evenly over the bricks:
+// at most kAdjTilesX x-tiles and kAdjMaxY rows per brick; the z split fills
+// whole rounds of resident workgroups.  A workgroup reads its brick's dfield exactly
+// once.  Each thread owns one x-tile of one row (lane = x-tile, 16 tiles x 4
+// rows per wave) and marches along z.  At every voxel plane it loads the tile
+// row's dx voxels (contiguous) and forms the four x-moments
+//   M_l = sum_o Bx_l(o) * dfield[z][y][tx*dx + o]          (l = 0..3)
+// with weights that are the same for every lane, then accumulates them into
+// the four control planes the current z-tile touches,
+//   A[n][l] += Bz_n(w) * M_l                                  (n = cz - tz).
+// When a z-tile ends, plane A[0] is finished; the workgroup combines it in LDS
+//   Sx[y][cx] = sum_l A[0][l] of tile (cx - l)
 //   G[cy][cx] = sum_m sum_{y in tile cy-m} By_m(v(y)) * Sx[y][cx]
-// G is the brick's partial gradient for that control plane; every brick writes
-// its whole window of (cz, cy, cx) partials to the workspace.
+// and writes G, the brick's partial gradient of that control plane.  Every
+// brick writes its whole window of (cz, cy, cx) partials to the workspace.
 //
 // Pass 2 (one thread per control point) sums the partials of the bricks whose
 // voxels touch the point (at most 2 per axis when a brick spans >= 3 tiles), in
-// fixed brick order.  No atomics anywhere, so the bits depend on the inputs only.
+// fixed brick order.  No atomics anywhere: the bits depend on the inputs only.
+//
+// The x-tile loop is specialised for spacings 1..kAdjMaxDX (fully unrolled, so
+// every load of a tile row is in flight at once); larger spacings use a generic
+// loop over chunks of kAdjChunk.  Both perform the same operations in the same
+// order.
 #pragma once
 
 #include "bsi_device.h"
 
 namespace bsi {
 
-// Workgroup shape of pass 1 (compile-time; the brick is always at most 64 x 32
-// voxels in x, y, so these knobs change scheduling, never the summation order).
-#ifndef BSI_ADJ_WAVES
-#define BSI_ADJ_WAVES 8
+#ifndef BSI_ADJ_TILES_X
+#define BSI_ADJ_TILES_X 16
 #endif
-#ifndef BSI_ADJ_PREFETCH
-#define BSI_ADJ_PREFETCH 2
+constexpr int kAdjTilesX = BSI_ADJ_TILES_X;        // x-tiles per brick (= lanes per row)
+constexpr int kAdjThreads = 512;
+constexpr int kAdjMaxY = kAdjThreads / kAdjTilesX;  // rows per brick
+constexpr int kAdjMaxCx = kAdjTilesX + 4;           // window bound in x
+// Workgroups of pass 1 resident at once on MI355X (256 CUs x 2).  The z split
+// is chosen so the brick count fills whole rounds of these slots; it is a
+// constant of the library, not a property queried from the device, so the
+// decomposition (and the bits) never depend on the GPU it runs on.
+constexpr int kAdjSlots = 512;
+#ifndef BSI_ADJ_TARGET_Z
+#define BSI_ADJ_TARGET_Z 24
 #endif
-constexpr int kAdjWaves = BSI_ADJ_WAVES;
-constexpr int kAdjThreads = kWave * kAdjWaves;
-constexpr int kAdjMaxX = kWave;                  // 64
-constexpr int kAdjMaxY = 32;
-constexpr int kAdjRows = kAdjMaxY / kAdjWaves;   // rows per thread
-constexpr int kAdjPrefetch = BSI_ADJ_PREFETCH;   // z-planes loaded ahead
-constexpr int kAdjMaxCx = (kAdjMaxX - 1) + 5;    // window bound at spacing 1
-constexpr int kAdjTargetZ = 24;
-static_assert(kAdjRows * kAdjWaves == kAdjMaxY, "rows must tile the 32-row brick");
-static_assert(kAdjPrefetch >= 1 && kAdjPrefetch <= 4, "prefetch depth 1..4");
+constexpr int kAdjTargetZ = BSI_ADJ_TARGET_Z;       // brick depth bound (voxels)
+constexpr int kAdjMaxDX = 8;                        // largest specialised x spacing
+constexpr int kAdjChunk = 4;                        // generic path: voxels per step
+static_assert(kWave % kAdjTilesX == 0, "a wave holds whole rows of tiles");
+
+constexpr int kAdjWaves = kAdjThreads / kWave;
+// Per-wave LDS region: the wave's tile rows of one voxel plane (64 * dx voxels,
+// for dx <= kAdjMaxDX) on their way from coalesced loads to tile-owning lanes;
+// between planes it also holds the wave's finished-plane entries (12 floats
+// per thread) for the emission.  Each wave only writes its own region.
+constexpr int kAdjWaveBuf = (kWave * kAdjMaxDX * 3 > kWave * 12) ? kWave * kAdjMaxDX * 3 : kWave * 12;
 
 struct AdjSmem {
-  float V[kAdjMaxY * kAdjMaxX * 3];    // finished plane A(x, y), per component
-  float Sx[kAdjMaxY * kAdjMaxCx * 3];  // x-contracted plane
-  float WX[kAdjMaxX * 4];              // Bx_l at each x of the brick
-  float WY[kAdjMaxY * 4];              // By_m at each y of the brick
+  float T[kAdjWaves * kAdjWaveBuf];      // per-wave transpose buffer / finished-plane entries
+  float Sx[kAdjMaxY * kAdjMaxCx * 3];    // x-combined plane
+  float WY[kAdjMaxY * 4];                // By_m at each y of the brick
 };
+
+// Entry of thread t = yl * kAdjTilesX + txl (its finished plane, 12 floats).
+__device__ __forceinline__ float* adj_entry(AdjSmem& sm, int t) {
+  return sm.T + (t / kWave) * kAdjWaveBuf + (t % kWave) * 12;
+}
+
+// Order this wave's LDS writes before its following LDS reads (and vice versa):
+// lanes exchange data through the wave's own region, no workgroup barrier.
+// The fences name the LDS ("local") address space only: a fence without an
+// address space would also order global memory, i.e. wait for the wave's
+// outstanding prefetch loads.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
 
 struct AdjBrick {
   int x0, y0, z0, xe, ye, ze;  // voxel range [x0, xe) etc.
   int cx0, cy0, cz0;           // first control index of the window
   int Cx, Cy;                  // window extent in x, y
+  int ntx;                     // x-tiles of the brick inside the volume
 };
 
 __device__ __forceinline__ AdjBrick adj_brick_geom(const AdjGeom& a, int brick) {
   const VolGeom& g = a.g;
   AdjBrick b;
-  const int bx = brick % a.nbx;
-  const int t = brick / a.nbx;
-  const int by = t % a.nby;
-  const int bz = t / a.nby;
-  b.x0 = bx * a.xb;
-  b.y0 = by * a.yb;
-  b.z0 = bz * a.zb;
-  b.xe = min(b.x0 + a.xb, g.nx);
-  b.ye = min(b.y0 + a.yb, g.ny);
-  b.ze = min(b.z0 + a.zb, g.nz);
+  const int bx = brick % a.x.nb;
+  const int t = brick / a.x.nb;
+  const int by = t % a.y.nb;
+  const int bz = t / a.y.nb;
+  b.x0 = adj_brick_begin(a.x, g.nx, bx);
+  b.y0 = adj_brick_begin(a.y, g.ny, by);
+  b.z0 = adj_brick_begin(a.z, g.nz, bz);
+  b.xe = adj_brick_begin(a.x, g.nx, bx + 1);
+  b.ye = adj_brick_begin(a.y, g.ny, by + 1);
+  b.ze = adj_brick_begin(a.z, g.nz, bz + 1);
   b.cx0 = b.x0 / g.dx;
   b.cy0 = b.y0 / g.dy;
   b.cz0 = b.z0 / g.dz;
   b.Cx = (b.xe - 1) / g.dx - b.cx0 + 4;
   b.Cy = (b.ye - 1) / g.dy - b.cy0 + 4;
+  b.ntx = (b.xe - 1) / g.dx - b.cx0 + 1;
   return b;
 }
 
 // Contract one finished control plane (czl = cz - cz0) of the brick over x and
 // y and write the partials.  Collective: every thread of the workgroup calls it.
+// v[l] = A[0][l] of this thread's (row, tile); zero for idle threads.
 __device__ __forceinline__ void adj_emit(const AdjGeom& a, const AdjBrick& b, float* __restrict__ pbase,
-                                         AdjSmem& sm, int tid, int czl, const F3 (&v)[kAdjRows],
-                                         const bool (&act)[kAdjRows]) {
+                                         AdjSmem& sm, int tid, int czl, const F3 (&v)[4]) {
   const VolGeom& g = a.g;
-  const int lane = tid & (kWave - 1), w = tid / kWave;
+  {
+    wave_lds_sync();  // this wave's reads of its region (the plane's tile rows) come first
+    float* e = adj_entry(sm, tid);
 #pragma unroll
-  for (int k = 0; k < kAdjRows; ++k) {
-    const int yl = k * kAdjWaves + w;
-    float* d = sm.V + (yl * kAdjMaxX + lane) * 3;
-    d[0] = act[k] ? v[k].x : 0.f;
-    d[1] = act[k] ? v[k].y : 0.f;
-    d[2] = act[k] ? v[k].z : 0.f;
+    for (int l = 0; l < 4; ++l) {
+      e[3 * l] = v[l].x;
+      e[3 * l + 1] = v[l].y;
+      e[3 * l + 2] = v[l].z;
+    }
   }
   __syncthreads();
 
-  // x-contraction: one item per (row, cx), all three components
-  const int txlo = b.x0 / g.dx, txhi = (b.xe - 1) / g.dx;
-  const int n1 = (b.ye - b.y0) * b.Cx;
+  // x-combination: Sx[y][cx] = sum over l of A[0][l] of tile cx - l (l ascending)
+  const int rows = b.ye - b.y0;
+  const int n1 = rows * b.Cx;
   for (int it = tid; it < n1; it += kAdjThreads) {
     const int yl = it / b.Cx;
     const int cxl = it - yl * b.Cx;
-    const int cx = b.cx0 + cxl;
-    const float* vrow = sm.V + yl * kAdjMaxX * 3;
     float sx = 0.f, sy = 0.f, sz = 0.f;
+#pragma unroll
     for (int l = 0; l < 4; ++l) {
-      const int tile = cx - l;
-      if (tile < txlo || tile > txhi) continue;
-      const int xa = max(tile * g.dx, b.x0) - b.x0;
-      const int xb = min(tile * g.dx + g.dx, b.xe) - b.x0;
-#pragma unroll 4
-      for (int xl = xa; xl < xb; ++xl) {
-        const float wv = sm.WX[xl * 4 + l];
-        const float* v = vrow + xl * 3;
-        sx = fmaf(wv, v[0], sx);
-        sy = fmaf(wv, v[1], sy);
-        sz = fmaf(wv, v[2], sz);
+      const int txl = cxl - l;
+      if (txl >= 0 && txl < b.ntx) {
+        const float* e = adj_entry(sm, yl * kAdjTilesX + txl) + l * 3;
+        sx += e[0];
+        sy += e[1];
+        sz += e[2];
       }
     }
     float* o = sm.Sx + (yl * kAdjMaxCx + cxl) * 3;
@@ -137,36 +167,126 @@ __device__ __forceinline__ void adj_emit(const AdjGeom& a, const AdjBrick& b, fl
 #pragma unroll 4
       for (int yl = ya; yl < yb; ++yl) {
         const float wv = sm.WY[yl * 4 + m];
-        const float* v = sm.Sx + (yl * kAdjMaxCx + cxl) * 3;
-        sx = fmaf(wv, v[0], sx);
-        sy = fmaf(wv, v[1], sy);
-        sz = fmaf(wv, v[2], sz);
+        const float* s = sm.Sx + (yl * kAdjMaxCx + cxl) * 3;
+        sx = fmaf(wv, s[0], sx);
+        sy = fmaf(wv, s[1], sy);
+        sz = fmaf(wv, s[2], sz);
       }
     }
-    stf3(pbase + ((size_t)(czl * a.cym + cyl) * a.cxm + cxl) * 3, F3{sx, sy, sz});
+    stf3(pbase + ((size_t)(czl * a.y.cm + cyl) * a.x.cm + cxl) * 3, F3{sx, sy, sz});
   }
   // No trailing barrier: the next emit's first barrier orders these LDS reads
-  // before its Sx writes, and its V writes come after this emit's second barrier.
+  // before its Sx writes.  The entries (read before the second barrier) share
+  // each wave's region with the next plane's tile rows, which the wave writes
+  // only after that barrier.
+}
+
+// One step of the x-moments: voxel o of the tile row with value d.
+__device__ __forceinline__ void adj_xmoment_step(int o, const float* __restrict__ w, const F3& d, F3 (&M)[4]) {
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    if (o == 0) {
+      M[l].x = w[l] * d.x;
+      M[l].y = w[l] * d.y;
+      M[l].z = w[l] * d.z;
+    } else {
+      M[l].x = fmaf(w[l], d.x, M[l].x);
+      M[l].y = fmaf(w[l], d.y, M[l].y);
+      M[l].z = fmaf(w[l], d.z, M[l].z);
+    }
+  }
+}
+
+// x-moments of one tile row: M_l = sum_o Bx_l(o) d(o), o ascending, over the
+// voxels o < nval of the tile (nval < dx only for the volume's last tile; 0
+// for idle threads, which then keep M = 0).  DX > 0: compile-time spacing, all
+// loads issued together (adj_row_load / adj_row_moments, so the next plane's
+// row can be in flight while this one is reduced).  DX == 0: runtime spacing,
+// chunks of kAdjChunk loads.
+// Coalesced loads of the wave's part of one voxel plane, for DX <= kAdjMaxDX:
+// the wave's kAdjRowsPerWave rows x (kAdjTilesX * DX) voxels, enumerated
+// v = row * kAdjTilesX * DX + x; lane j loads v = k * 64 + j (k < DX), i.e.
+// consecutive lanes read consecutive 12-byte voxels.
+constexpr int kAdjRowsPerWave = kWave / kAdjTilesX;
+
+template <int DX>
+__device__ __forceinline__ void adj_plane_load(const float* __restrict__ plane, const AdjBrick& b, int nx,
+                                               int ywave, int lane, F3 (&d)[DX]) {
+  // Every lane loads from a valid address, clamped into the brick, with no
+  // branch or select around the load (the data is only consumed one plane
+  // later).  A clamped slot holds a copy of another voxel, but no lane reads
+  // it: tile rows stop at the volume (nval) and rows outside the brick belong
+  // to idle lanes.
+#pragma unroll
+  for (int k = 0; k < DX; ++k) {
+    const int v = k * kWave + lane;
+    const int r = v / (kAdjTilesX * DX);
+    const int xl = v - r * (kAdjTilesX * DX);
+    const int x = min(b.x0 + xl, b.xe - 1), y = min(ywave + r, b.ye - 1);
+    d[k] = ldf3(plane + ((size_t)y * nx + x) * 3);
+  }
+}
+
+// Stage a loaded plane in the wave's LDS region (lanes exchange data: tile rows
+// come out of coalesced loads).
+template <int DX>
+__device__ __forceinline__ void adj_plane_stage(float* __restrict__ buf, int lane, const F3 (&d)[DX]) {
+  wave_lds_sync();  // previous readers of the region are done
+#pragma unroll
+  for (int k = 0; k < DX; ++k) stf3(buf + (k * kWave + lane) * 3, d[k]);
+  wave_lds_sync();
+}
+
+// x-moments of this lane's tile row (row r = lane / kAdjTilesX, tile
+// txl = lane % kAdjTilesX), read from the staged plane: rows of up to 5 voxels
+// at once, longer rows in chunks of kAdjChunk (the chunk loop stays rolled, so
+// the register footprint does not grow with the spacing).  Same
+// operations, same order as adj_xmoments_generic.
+template <int DX>
+__device__ __forceinline__ void adj_plane_moments(const float* __restrict__ buf, int lane, int nval,
+                                                  const float* __restrict__ lutx, F3 (&M)[4]) {
+  constexpr int C = DX <= 5 ? DX : kAdjChunk;  // short rows in one chunk
+  const int r = lane / kAdjTilesX, txl = lane % kAdjTilesX;
+  const float* p = buf + (r * kAdjTilesX * DX + txl * DX) * 3;
+#pragma unroll
+  for (int l = 0; l < 4; ++l) M[l] = F3{0.f, 0.f, 0.f};
+#pragma unroll 1
+  for (int o0 = 0; o0 < DX; o0 += C) {
+    F3 v[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) v[j] = o0 + j < DX ? ldf3(p + 3 * (o0 + j)) : F3{0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < C; ++j)
+      if (o0 + j < nval) adj_xmoment_step(o0 + j, lutx + 4 * (o0 + j), v[j], M);
+  }
+}
+
+
+__device__ __forceinline__ void adj_xmoments_generic(const float* __restrict__ row, int nval,
+                                                     const float* __restrict__ lutx, F3 (&M)[4]) {
+#pragma unroll
+  for (int l = 0; l < 4; ++l) M[l] = F3{0.f, 0.f, 0.f};
+  for (int o0 = 0; o0 < nval; o0 += kAdjChunk) {
+    F3 d[kAdjChunk];
+#pragma unroll
+    for (int j = 0; j < kAdjChunk; ++j) d[j] = o0 + j < nval ? ldf3(row + 3 * (o0 + j)) : F3{0.f, 0.f, 0.f};
+#pragma unroll
+    for (int j = 0; j < kAdjChunk; ++j)
+      if (o0 + j < nval) adj_xmoment_step(o0 + j, lutx + 4 * (o0 + j), d[j], M);
+  }
 }
 
 // Pass 1 for one brick.  Collective over the workgroup (kAdjThreads threads).
+template <int DX>
 __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, float* __restrict__ part,
                                           const AdjGeom& a, const float* __restrict__ lut, int brick,
                                           AdjSmem& sm, int tid) {
   const VolGeom& g = a.g;
+  const int dx = DX > 0 ? DX : g.dx;
   const AdjBrick b = adj_brick_geom(a, brick);
-  float* pbase = part + (size_t)brick * a.czm * a.cym * a.cxm * 3;
+  float* pbase = part + (size_t)brick * a.z.cm * a.y.cm * a.x.cm * 3;
 
-  __syncthreads();  // a previous brick of this workgroup may still read WX / WY
-  for (int i = tid; i < kAdjMaxX * 4; i += kAdjThreads) {
-    const int x = b.x0 + (i >> 2);
-    float wv = 0.f;
-    if (x < b.xe) {
-      const int t = x / g.dx;
-      wv = lut_row(lut, g.dx, x - t * g.dx)[i & 3];
-    }
-    sm.WX[i] = wv;
-  }
+  __syncthreads();  // a previous brick of this workgroup may still read WY
   for (int i = tid; i < kAdjMaxY * 4; i += kAdjThreads) {
     const int y = b.y0 + (i >> 2);
     float wv = 0.f;
@@ -178,85 +298,90 @@ __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, floa
   }
   // (the first adj_emit barrier orders these writes before any read)
 
-  const int lane = tid & (kWave - 1), w = tid / kWave;
-  const int x = b.x0 + lane;
+  const int txl = tid % kAdjTilesX;
+  const int yl = tid / kAdjTilesX;
+  const int y = b.y0 + yl;
+  const int tx = b.cx0 + txl;
+  const bool act = txl < b.ntx && y < b.ye;
+  const int x = tx * dx;
+  const int nval = act ? min(dx, g.nx - x) : 0;  // voxels of this tile row
   const size_t zs = (size_t)g.ny * g.nx * 3;
-  bool act[kAdjRows];
-  const float* src[kAdjRows];
-#pragma unroll
-  for (int k = 0; k < kAdjRows; ++k) {
-    const int y = b.y0 + k * kAdjWaves + w;
-    act[k] = (x < b.xe) && (y < b.ye);
-    src[k] = dfield + (((size_t)b.z0 * g.ny + (act[k] ? y : 0)) * g.nx + (act[k] ? x : 0)) * 3;
-  }
+  const float* src = dfield + (((size_t)b.z0 * g.ny + (act ? y : 0)) * g.nx + (act ? x : 0)) * 3;
+  const float* lutx = lut_row(lut, dx, 0);
 
-  F3 acc[kAdjRows][4];
+  F3 acc[4][4];  // [n][l]
 #pragma unroll
-  for (int k = 0; k < kAdjRows; ++k)
+  for (int n = 0; n < 4; ++n)
 #pragma unroll
-    for (int n = 0; n < 4; ++n) acc[k][n] = F3{0.f, 0.f, 0.f};
-
-  const F3 zero{0.f, 0.f, 0.f};
-  // ring of the next kAdjPrefetch z-planes of every row (registers)
-  F3 pf[kAdjPrefetch][kAdjRows];
-#pragma unroll
-  for (int j = 0; j < kAdjPrefetch; ++j)
-#pragma unroll
-    for (int k = 0; k < kAdjRows; ++k)
-      pf[j][k] = (act[k] && b.z0 + j < b.ze) ? ldf3(src[k] + (size_t)j * zs) : zero;
+    for (int l = 0; l < 4; ++l) acc[n][l] = F3{0.f, 0.f, 0.f};
 
   int tz = b.cz0;
   int oz = b.z0 - tz * g.dz;
-  for (int z = b.z0; z < b.ze; ++z) {
-    F3 cur[kAdjRows];
-#pragma unroll
-    for (int k = 0; k < kAdjRows; ++k) {
-      cur[k] = pf[0][k];
-#pragma unroll
-      for (int j = 0; j + 1 < kAdjPrefetch; ++j) pf[j][k] = pf[j + 1][k];
-      const int zn = z + kAdjPrefetch;
-      pf[kAdjPrefetch - 1][k] = (act[k] && zn < b.ze) ? ldf3(src[k] + (size_t)(zn - b.z0) * zs) : zero;
-    }
+  const int lane = tid & (kWave - 1);
+  const int ywave = b.y0 + (tid / kWave) * kAdjRowsPerWave;
+  float* wbuf = sm.T + (tid / kWave) * kAdjWaveBuf;
+  const float* plane0 = dfield + (size_t)b.z0 * zs;
+
+  // One voxel plane: x-moments of this lane's tile row, z-accumulation, and the
+  // emission of the finished control plane when a z-tile ends.
+  auto step = [&](const F3* M, int z) {
     const float* wz = lut_row(lut, g.dz, oz);
-    const float w0 = wz[0], w1 = wz[1], w2 = wz[2], w3 = wz[3];
 #pragma unroll
-    for (int k = 0; k < kAdjRows; ++k) {
-      acc[k][0].x = fmaf(w0, cur[k].x, acc[k][0].x);
-      acc[k][0].y = fmaf(w0, cur[k].y, acc[k][0].y);
-      acc[k][0].z = fmaf(w0, cur[k].z, acc[k][0].z);
-      acc[k][1].x = fmaf(w1, cur[k].x, acc[k][1].x);
-      acc[k][1].y = fmaf(w1, cur[k].y, acc[k][1].y);
-      acc[k][1].z = fmaf(w1, cur[k].z, acc[k][1].z);
-      acc[k][2].x = fmaf(w2, cur[k].x, acc[k][2].x);
-      acc[k][2].y = fmaf(w2, cur[k].y, acc[k][2].y);
-      acc[k][2].z = fmaf(w2, cur[k].z, acc[k][2].z);
-      acc[k][3].x = fmaf(w3, cur[k].x, acc[k][3].x);
-      acc[k][3].y = fmaf(w3, cur[k].y, acc[k][3].y);
-      acc[k][3].z = fmaf(w3, cur[k].z, acc[k][3].z);
+    for (int n = 0; n < 4; ++n) {
+      const float w = wz[n];
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        acc[n][l].x = fmaf(w, M[l].x, acc[n][l].x);
+        acc[n][l].y = fmaf(w, M[l].y, acc[n][l].y);
+        acc[n][l].z = fmaf(w, M[l].z, acc[n][l].z);
+      }
     }
     if (++oz == g.dz && z + 1 < b.ze) {
-      F3 fin[kAdjRows];
+      F3 fin[4];
 #pragma unroll
-      for (int k = 0; k < kAdjRows; ++k) fin[k] = acc[k][0];
-      adj_emit(a, b, pbase, sm, tid, tz - b.cz0, fin, act);
+      for (int l = 0; l < 4; ++l) fin[l] = acc[0][l];
+      adj_emit(a, b, pbase, sm, tid, tz - b.cz0, fin);
 #pragma unroll
-      for (int k = 0; k < kAdjRows; ++k) {
-        acc[k][0] = acc[k][1];
-        acc[k][1] = acc[k][2];
-        acc[k][2] = acc[k][3];
-        acc[k][3] = zero;
+      for (int l = 0; l < 4; ++l) {
+        acc[0][l] = acc[1][l];
+        acc[1][l] = acc[2][l];
+        acc[2][l] = acc[3][l];
+        acc[3][l] = F3{0.f, 0.f, 0.f};
       }
       oz = 0;
       ++tz;
+    }
+  };
+
+  if constexpr (DX > 0) {
+    // Per plane: wait for its loads (issued one plane earlier), stage them in
+    // LDS, which frees the registers, issue the next plane's loads into them,
+    // then read back this lane's tile row and reduce it.  One plane of loads is
+    // always in flight while the previous one is reduced (and emitted).
+    F3 d[DX];
+    adj_plane_load<DX>(plane0, b, g.nx, ywave, lane, d);
+    for (int z = b.z0; z < b.ze; ++z) {
+      adj_plane_stage<DX>(wbuf, lane, d);
+      if (z + 1 < b.ze) adj_plane_load<DX>(plane0 + (size_t)(z + 1 - b.z0) * zs, b, g.nx, ywave, lane, d);
+      F3 M[4];
+      adj_plane_moments<DX>(wbuf, lane, nval, lutx, M);
+      step(M, z);
+    }
+  } else {
+    for (int z = b.z0; z < b.ze; ++z) {
+      F3 M[4];
+      adj_xmoments_generic(src, nval, lutx, M);
+      src += zs;
+      step(M, z);
     }
   }
   // The last tile's four planes (the last three are shared with the next brick).
 #pragma unroll
   for (int n = 0; n < 4; ++n) {
-    F3 fin[kAdjRows];
+    F3 fin[4];
 #pragma unroll
-    for (int k = 0; k < kAdjRows; ++k) fin[k] = acc[k][n];
-    adj_emit(a, b, pbase, sm, tid, tz - b.cz0 + n, fin, act);
+    for (int l = 0; l < 4; ++l) fin[l] = acc[n][l];
+    adj_emit(a, b, pbase, sm, tid, tz - b.cz0 + n, fin);
   }
 }
 
@@ -264,20 +389,23 @@ __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, floa
 __device__ __forceinline__ F3 adj_gather_point(const float* __restrict__ part, const AdjGeom& a, int cx,
                                                int cy, int cz) {
   const VolGeom& g = a.g;
-  // bricks whose voxels touch the point's support [(c-3)d, (c+1)d) on each axis
-  const int bxlo = max(0, (cx - 3) * g.dx) / a.xb, bxhi = (min(g.nx, (cx + 1) * g.dx) - 1) / a.xb;
-  const int bylo = max(0, (cy - 3) * g.dy) / a.yb, byhi = (min(g.ny, (cy + 1) * g.dy) - 1) / a.yb;
-  const int bzlo = max(0, (cz - 3) * g.dz) / a.zb, bzhi = (min(g.nz, (cz + 1) * g.dz) - 1) / a.zb;
-  const size_t bstride = (size_t)a.czm * a.cym * a.cxm * 3;
+  // bricks whose voxels meet the point's support [(c-3)d, (c+1)d) on each axis
+  const int bxlo = adj_brick_of_voxel(a.x, max(0, (cx - 3) * g.dx));
+  const int bxhi = adj_brick_of_voxel(a.x, min(g.nx, (cx + 1) * g.dx) - 1);
+  const int bylo = adj_brick_of_voxel(a.y, max(0, (cy - 3) * g.dy));
+  const int byhi = adj_brick_of_voxel(a.y, min(g.ny, (cy + 1) * g.dy) - 1);
+  const int bzlo = adj_brick_of_voxel(a.z, max(0, (cz - 3) * g.dz));
+  const int bzhi = adj_brick_of_voxel(a.z, min(g.nz, (cz + 1) * g.dz) - 1);
+  const size_t bstride = (size_t)a.z.cm * a.y.cm * a.x.cm * 3;
   F3 s{0.f, 0.f, 0.f};
   for (int bz = bzlo; bz <= bzhi; ++bz) {
-    const int czl = cz - (bz * a.zb) / g.dz;
+    const int czl = cz - adj_brick_begin(a.z, g.nz, bz) / g.dz;
     for (int by = bylo; by <= byhi; ++by) {
-      const int cyl = cy - (by * a.yb) / g.dy;
+      const int cyl = cy - adj_brick_begin(a.y, g.ny, by) / g.dy;
       for (int bx = bxlo; bx <= bxhi; ++bx) {
-        const int cxl = cx - (bx * a.xb) / g.dx;
-        const float* p = part + (size_t)((bz * a.nby + by) * a.nbx + bx) * bstride +
-                         ((size_t)(czl * a.cym + cyl) * a.cxm + cxl) * 3;
+        const int cxl = cx - adj_brick_begin(a.x, g.nx, bx) / g.dx;
+        const float* p = part + (size_t)((bz * a.y.nb + by) * a.x.nb + bx) * bstride +
+                         ((size_t)(czl * a.y.cm + cyl) * a.x.cm + cxl) * 3;
         const F3 v = ldf3(p);
         s.x += v.x;
         s.y += v.y;

@@ -39,6 +39,8 @@ struct VolDesc {
 };
 
 enum Pass { kFwd = 0, kAdj1 = 1, kAdj2 = 2 };
+constexpr int kNumClasses = kAdjMaxDX + 1;  // class dx for dx <= kAdjMaxDX, class 0 otherwise
+inline int dx_class(int dx) { return dx <= kAdjMaxDX ? dx : 0; }
 constexpr int kPtThreads = 256;
 
 struct Schedule {
@@ -108,6 +110,10 @@ __global__ __launch_bounds__(kFwdThreads) void batch_fwd_kernel(const VolDesc* _
   }
 }
 
+// Pass 1 over the volumes of one x-spacing class (DX = 1..kAdjMaxDX, or 0 for
+// the generic path), each class with its own descriptor sub-table, so every
+// launch keeps the register footprint of its own specialisation.
+template <int DX>
 __global__ __launch_bounds__(kAdjThreads) void batch_adj1_kernel(const VolDesc* __restrict__ vols, int count,
                                                                   int64_t total, int chunked,
                                                                   const float* __restrict__ lut) {
@@ -117,7 +123,7 @@ __global__ __launch_bounds__(kAdjThreads) void batch_adj1_kernel(const VolDesc* 
     const int vi = uniform(find_volume(vols, count, item, kAdj1));
     const VolDesc& d = vols[vi];
     const AdjGeom a = d.a;
-    adj_brick(d.dfield, d.part, a, lut, (int)(item - d.first[kAdj1]), sm, threadIdx.x);
+    adj_brick<DX>(d.dfield, d.part, a, lut, (int)(item - d.first[kAdj1]), sm, threadIdx.x);
   }
 }
 
@@ -152,6 +158,12 @@ struct bsi_batch {
   std::vector<size_t> part_off;
   int64_t total[3] = {0, 0, 0};
   VolDesc* d_desc = nullptr;
+  // Pass 1 runs one launch per x-spacing class (see batch_adj1_kernel): the
+  // descriptors again, ordered by class, with pass-1 item indices per class.
+  std::vector<VolDesc> cls_host;
+  int cls_first[kNumClasses + 1] = {};  // class c holds cls_host[cls_first[c] .. cls_first[c+1])
+  int64_t cls_total[kNumClasses] = {};
+  VolDesc* d_cls = nullptr;
   float* d_part = nullptr;
   const float* lut = nullptr;
   bool has_fwd = false, has_adj = false;
@@ -191,15 +203,36 @@ hipError_t launch_pass(bsi_batch* p, int pass, hipStream_t s) {
   int64_t grid = per_cu == 0 ? total : std::min<int64_t>(total, (int64_t)per_cu * p->cus);
   if (grid > 0x7fffffff) grid = 0x7fffffff;
   const int chunked = per_cu == 0 ? 0 : sc.chunked;
-  if (pass == kFwd)
+  if (pass == kFwd) {
     hipLaunchKernelGGL(batch_fwd_kernel, dim3((unsigned)grid), dim3(kFwdThreads), 0, s, p->d_desc,
                        p->count, total, chunked, p->lut);
-  else if (pass == kAdj1)
-    hipLaunchKernelGGL(batch_adj1_kernel, dim3((unsigned)grid), dim3(kAdjThreads), 0, s, p->d_desc, p->count,
-                       total, chunked, p->lut);
-  else
+  } else if (pass == kAdj1) {
+    for (int c = 0; c < kNumClasses; ++c) {
+      const int n = p->cls_first[c + 1] - p->cls_first[c];
+      const int64_t ct = p->cls_total[c];
+      if (n == 0 || ct == 0) continue;
+      const int64_t cg = per_cu == 0 ? ct : std::min<int64_t>(ct, (int64_t)per_cu * p->cus);
+      const dim3 gd((unsigned)cg), bd(kAdjThreads);
+      const VolDesc* v = p->d_cls + p->cls_first[c];
+      switch (c) {
+        case 1: hipLaunchKernelGGL(batch_adj1_kernel<1>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+        case 2: hipLaunchKernelGGL(batch_adj1_kernel<2>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+        case 3: hipLaunchKernelGGL(batch_adj1_kernel<3>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+        case 4: hipLaunchKernelGGL(batch_adj1_kernel<4>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+        case 5: hipLaunchKernelGGL(batch_adj1_kernel<5>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+        case 6: hipLaunchKernelGGL(batch_adj1_kernel<6>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+        case 7: hipLaunchKernelGGL(batch_adj1_kernel<7>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+        case 8: hipLaunchKernelGGL(batch_adj1_kernel<8>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+        default: hipLaunchKernelGGL(batch_adj1_kernel<0>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+      }
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  } else {
     hipLaunchKernelGGL(batch_adj2_kernel, dim3((unsigned)grid), dim3(kPtThreads), 0, s, p->d_desc, p->count,
                        total, chunked);
+  }
   return hipGetLastError();
 }
 
@@ -323,7 +356,7 @@ int32_t bsi_batch_create(int32_t count, const int32_t* dims3xN, const int32_t* s
     d.first[kAdj1] = tot[kAdj1];
     d.first[kAdj2] = tot[kAdj2];
     tot[kFwd] += (int64_t)d.f.nbx * d.f.nby * d.f.nbz;
-    tot[kAdj1] += (int64_t)d.a.nbx * d.a.nby * d.a.nbz;
+    tot[kAdj1] += (int64_t)d.a.x.nb * d.a.y.nb * d.a.z.nb;
     tot[kAdj2] += ((int64_t)g.gx * g.gy * g.gz + kPtThreads - 1) / kPtThreads;
   }
   int dev = 0;
@@ -352,6 +385,24 @@ int32_t bsi_batch_create(int32_t count, const int32_t* dims3xN, const int32_t* s
     return BSI_ERR_NOMEM;
   }
   for (int i = 0; i < count; ++i) p->host[i].part = p->d_part + p->part_off[i];
+  // class-ordered copy for pass 1, with item indices restarting per class
+  for (int c = 0; c < kNumClasses; ++c) {
+    p->cls_first[c] = (int)p->cls_host.size();
+    for (int i = 0; i < count; ++i) {
+      if (dx_class(p->host[i].a.g.dx) != c) continue;
+      VolDesc d = p->host[i];
+      d.first[kAdj1] = p->cls_total[c];
+      p->cls_total[c] += (int64_t)d.a.x.nb * d.a.y.nb * d.a.z.nb;
+      p->cls_host.push_back(d);
+    }
+  }
+  p->cls_first[kNumClasses] = (int)p->cls_host.size();
+  if (hipMalloc(&p->d_cls, sizeof(VolDesc) * (size_t)count) != hipSuccess) {
+    (void)hipGetLastError();
+    bsi_batch_destroy(p);
+    set_error("out of device memory for the batched plan");
+    return BSI_ERR_NOMEM;
+  }
   if ((e = hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking)) != hipSuccess ||
       (e = hipEventCreateWithFlags(&p->fork, hipEventDisableTiming)) != hipSuccess ||
       (e = hipEventCreateWithFlags(&p->join, hipEventDisableTiming)) != hipSuccess) {
@@ -398,9 +449,20 @@ int32_t bsi_batch_bind(bsi_batch* p, const float* const* grids, float* const* fi
   }
   p->has_fwd = grids != nullptr;
   p->has_adj = dfields != nullptr;
+  for (VolDesc& c : p->cls_host) {  // same buffers in the class-ordered copy
+    for (int i = 0; i < p->count; ++i)
+      if (p->host[i].part == c.part) {
+        c.grid = p->host[i].grid;
+        c.field = p->host[i].field;
+        c.dfield = p->host[i].dfield;
+        c.grad = p->host[i].grad;
+      }
+  }
   drop_graph(p);
   hipError_t e = hipMemcpy(p->d_desc, p->host.data(), sizeof(VolDesc) * p->host.size(), hipMemcpyHostToDevice);
-  return e == hipSuccess ? BSI_OK : hip_fail(e, "uploading the descriptor table");
+  if (e != hipSuccess) return hip_fail(e, "uploading the descriptor table");
+  e = hipMemcpy(p->d_cls, p->cls_host.data(), sizeof(VolDesc) * p->cls_host.size(), hipMemcpyHostToDevice);
+  return e == hipSuccess ? BSI_OK : hip_fail(e, "uploading the class descriptor table");
 }
 
 int32_t bsi_batch_config(const bsi_batch* p, int32_t* index, int32_t* count) {
@@ -552,6 +614,7 @@ void bsi_batch_destroy(bsi_batch* p) {
   if (p->join) (void)hipEventDestroy(p->join);
   if (p->side) (void)hipStreamDestroy(p->side);
   if (p->d_desc) (void)hipFree(p->d_desc);
+  if (p->d_cls) (void)hipFree(p->d_cls);
   if (p->d_part) (void)hipFree(p->d_part);
   if (prev >= 0) (void)hipSetDevice(prev);
   delete p;

@@ -29,14 +29,30 @@ struct VolGeom {
   int32_t gx, gy, gz;  // control points = ceil(n/d) + 3
 };
 
-// Brick decomposition of the adjoint (see adjoint.hip).  A pure function of the
+// Brick decomposition of the adjoint along one axis: the axis is cut into U
+// units of u voxels (a tile, or a single voxel when a tile is taller than a
+// brick may be), and brick b of nb holds units [b*U/nb, (b+1)*U/nb) (integer
+// division: sizes differ by at most one unit).  cm bounds the number of control
+// points whose support meets one brick (the partial-window stride).
+struct AdjAxis {
+  int32_t u, U, nb, cm;
+};
+
+// The adjoint's bricks (see adjoint_device.h).  A pure function of the
 // geometry, so the summation order, and thus the bits, depend on the inputs only.
 struct AdjGeom {
   VolGeom g;
-  int32_t xb, yb, zb;     // brick extent in voxels
-  int32_t nbx, nby, nbz;  // bricks per axis
-  int32_t cxm, cym, czm;  // partial-window strides (upper bound of a brick window)
+  AdjAxis x, y, z;
 };
+
+__host__ __device__ __forceinline__ int adj_brick_begin(const AdjAxis& a, int n, int b) {
+  const int v = (int)(((int64_t)b * a.U / a.nb) * a.u);
+  return v < n ? v : n;
+}
+__host__ __device__ __forceinline__ int adj_brick_of_voxel(const AdjAxis& a, int v) {
+  const int t = v / a.u;
+  return (int)(((int64_t)(t + 1) * a.nb - 1) / a.U);
+}
 
 __device__ __forceinline__ const float* lut_row(const float* lut, int d, int o) {
   return lut + 4 * ((d * (d - 1)) / 2 + o);
