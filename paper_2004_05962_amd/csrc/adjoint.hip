@@ -9,7 +9,7 @@ template <int DX>
 __global__ __launch_bounds__(kAdjThreads) void adj_pass1_kernel(const float* __restrict__ dfield,
                                                                  float* __restrict__ part, AdjGeom a,
                                                                  const float* __restrict__ lut) {
-  __shared__ AdjSmem sm;
+  __shared__ AdjSmem<DX> sm;
   const int nbricks = a.x.nb * a.y.nb * a.z.nb;
   const int brick = xcd_remap(blockIdx.x, gridDim.x);
   if (brick >= nbricks) return;  // uniform over the workgroup

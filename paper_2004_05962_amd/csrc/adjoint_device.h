@@ -52,22 +52,27 @@ constexpr int kAdjChunk = 4;                        // generic path: voxels per 
 static_assert(kWave % kAdjTilesX == 0, "a wave holds whole rows of tiles");
 
 constexpr int kAdjWaves = kAdjThreads / kWave;
-// Per-wave LDS region: the wave's tile rows of one voxel plane (64 * dx voxels,
-// for dx <= kAdjMaxDX) on their way from coalesced loads to tile-owning lanes;
-// between planes it also holds the wave's finished-plane entries (12 floats
-// per thread) for the emission.  Each wave only writes its own region.
-constexpr int kAdjWaveBuf = (kWave * kAdjMaxDX * 3 > kWave * 12) ? kWave * kAdjMaxDX * 3 : kWave * 12;
+constexpr int kAdjRowsPerWave = kWave / kAdjTilesX;  // a wave holds whole rows of tiles
+constexpr int kAdjSlotsX = 4;  // x-combined planes buffered in LDS (two pairs)
 
+// Per-wave LDS region: the wave's tile rows of one voxel plane (64 * DX voxels)
+// on their way from coalesced loads to tile-owning lanes; between planes it
+// also holds the wave's finished-plane entries (12 floats per lane).  Each
+// wave only ever touches its own region.
+__host__ __device__ constexpr int adj_wave_buf(int dx) {
+  return (kWave * dx * 3 > kWave * 12) ? kWave * dx * 3 : kWave * 12;
+}
+
+constexpr int kAdjMaxCy = kAdjMaxY + 4;  // y-window bound (32 one-row units)
+
+template <int DX>
 struct AdjSmem {
-  float T[kAdjWaves * kAdjWaveBuf];      // per-wave transpose buffer / finished-plane entries
-  float Sx[kAdjMaxY * kAdjMaxCx * 3];    // x-combined plane
-  float WY[kAdjMaxY * 4];                // By_m at each y of the brick
+  float T[kAdjWaves * adj_wave_buf(DX)];              // per-wave transpose buffer / entries
+  float Sx[kAdjSlotsX * kAdjMaxY * kAdjMaxCx * 3];     // x-combined planes
+  float WYC[kAdjMaxCy * kAdjMaxY];                    // By weight of brick row y for window row cy
+  int YR[kAdjMaxCy * 2];                              // rows [ya, yb) of the brick in cy's support
 };
 
-// Entry of thread t = yl * kAdjTilesX + txl (its finished plane, 12 floats).
-__device__ __forceinline__ float* adj_entry(AdjSmem& sm, int t) {
-  return sm.T + (t / kWave) * kAdjWaveBuf + (t % kWave) * 12;
-}
 
 // Order this wave's LDS writes before its following LDS reads (and vice versa):
 // lanes exchange data through the wave's own region, no workgroup barrier.
@@ -109,15 +114,29 @@ __device__ __forceinline__ AdjBrick adj_brick_geom(const AdjGeom& a, int brick) 
   return b;
 }
 
-// Contract one finished control plane (czl = cz - cz0) of the brick over x and
-// y and write the partials.  Collective: every thread of the workgroup calls it.
-// v[l] = A[0][l] of this thread's (row, tile); zero for idle threads.
+// Finished control plane number k of the brick (czl = cz - cz0).  Collective:
+// every thread of the workgroup calls it.  v[l] = A[0][l] of this thread's
+// (row, tile); zero for idle threads.
+//  1. Each wave combines its own rows over x (its 4 rows hold all 16 tiles):
+//       Sx[y][cx] = sum over l of A[0][l] of tile cx - l   (l ascending)
+//     through its own LDS region, with no workgroup barrier, into slot k % 4.
+//  2. After every second plane (and after the brick's last one) one barrier,
+//     then the y-contraction of the buffered planes, over the brick rows in
+//     cy's support in ascending order:
+//       G[cy][cx] = sum_y By_{cy - floor(y/dy)}(v(y)) * Sx[y][cx]
+//     written to the brick's partials.
+// Slot reuse: plane k + 4 overwrites slot k % 4 only after the barrier of the
+// pair k + 2, k + 3, which every thread passes after its y-contraction of k.
+template <int DX>
 __device__ __forceinline__ void adj_emit(const AdjGeom& a, const AdjBrick& b, float* __restrict__ pbase,
-                                         AdjSmem& sm, int tid, int czl, const F3 (&v)[4]) {
-  const VolGeom& g = a.g;
+                                         AdjSmem<DX>& sm, int tid, int k, int czl, bool last,
+                                         const F3 (&v)[4]) {
+  const int lane = tid & (kWave - 1);
+  const int wave = tid / kWave;
+  float* wbuf = sm.T + wave * adj_wave_buf(DX);
+  wave_lds_sync();  // this wave's reads of its region (the plane's tile rows) come first
   {
-    wave_lds_sync();  // this wave's reads of its region (the plane's tile rows) come first
-    float* e = adj_entry(sm, tid);
+    float* e = wbuf + lane * 12;
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
       e[3 * l] = v[l].x;
@@ -125,60 +144,60 @@ __device__ __forceinline__ void adj_emit(const AdjGeom& a, const AdjBrick& b, fl
       e[3 * l + 2] = v[l].z;
     }
   }
-  __syncthreads();
-
-  // x-combination: Sx[y][cx] = sum over l of A[0][l] of tile cx - l (l ascending)
+  wave_lds_sync();
+  float* sx = sm.Sx + (k % kAdjSlotsX) * (kAdjMaxY * kAdjMaxCx * 3);
   const int rows = b.ye - b.y0;
-  const int n1 = rows * b.Cx;
-  for (int it = tid; it < n1; it += kAdjThreads) {
-    const int yl = it / b.Cx;
-    const int cxl = it - yl * b.Cx;
-    float sx = 0.f, sy = 0.f, sz = 0.f;
+  // lane -> (row r, window column cxl): columns 0..15 for all 4 rows, then the
+  // 3 columns past the last tile (lanes 0..11)
+#pragma unroll 1
+  for (int pass = 0; pass < 2; ++pass) {
+    const int r = pass == 0 ? lane / kAdjTilesX : lane / 3;
+    const int cxl = pass == 0 ? lane % kAdjTilesX : kAdjTilesX + lane % 3;
+    const int yl = wave * kAdjRowsPerWave + r;
+    if ((pass == 1 && lane >= 3 * kAdjRowsPerWave) || cxl >= b.Cx || yl >= rows) continue;
+    float ax = 0.f, ay = 0.f, az = 0.f;
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
       const int txl = cxl - l;
       if (txl >= 0 && txl < b.ntx) {
-        const float* e = adj_entry(sm, yl * kAdjTilesX + txl) + l * 3;
-        sx += e[0];
-        sy += e[1];
-        sz += e[2];
+        const float* e = wbuf + (r * kAdjTilesX + txl) * 12 + l * 3;
+        ax += e[0];
+        ay += e[1];
+        az += e[2];
       }
     }
-    float* o = sm.Sx + (yl * kAdjMaxCx + cxl) * 3;
-    o[0] = sx;
-    o[1] = sy;
-    o[2] = sz;
+    float* o = sx + (yl * kAdjMaxCx + cxl) * 3;
+    o[0] = ax;
+    o[1] = ay;
+    o[2] = az;
   }
-  __syncthreads();
+  if (!(k & 1) && !last) return;  // the y-contraction waits for the pair
 
-  // y-contraction: one item per (cy, cx), all three components
-  const int tylo = b.y0 / g.dy, tyhi = (b.ye - 1) / g.dy;
-  const int n2 = b.Cy * b.Cx;
-  for (int it = tid; it < n2; it += kAdjThreads) {
-    const int cyl = it / b.Cx;
-    const int cxl = it - cyl * b.Cx;
-    const int cy = b.cy0 + cyl;
-    float sx = 0.f, sy = 0.f, sz = 0.f;
-    for (int m = 0; m < 4; ++m) {
-      const int tile = cy - m;
-      if (tile < tylo || tile > tyhi) continue;
-      const int ya = max(tile * g.dy, b.y0) - b.y0;
-      const int yb = min(tile * g.dy + g.dy, b.ye) - b.y0;
+  __syncthreads();
+  const int npend = (k & 1) ? 2 : 1;  // planes k-1, k  or  k alone
+  // item -> (plane p, window row cyl, window column cxl), cxl = item % 32
+  for (int it = tid; it < npend * b.Cy * 32; it += kAdjThreads) {
+    const int cxl = it & 31;
+    const int pc = it >> 5;
+    const int p = pc >= b.Cy ? 1 : 0;
+    const int cyl = pc - p * b.Cy;
+    if (cxl >= b.Cx) continue;
+    const int kk = k - (npend - 1) + p;
+    const float* sp = sm.Sx + (kk % kAdjSlotsX) * (kAdjMaxY * kAdjMaxCx * 3) + cxl * 3;
+    const float* wrow = sm.WYC + cyl * kAdjMaxY;
+    const int ya = sm.YR[2 * cyl], yb = sm.YR[2 * cyl + 1];
+    float ax = 0.f, ay = 0.f, az = 0.f;
 #pragma unroll 4
-      for (int yl = ya; yl < yb; ++yl) {
-        const float wv = sm.WY[yl * 4 + m];
-        const float* s = sm.Sx + (yl * kAdjMaxCx + cxl) * 3;
-        sx = fmaf(wv, s[0], sx);
-        sy = fmaf(wv, s[1], sy);
-        sz = fmaf(wv, s[2], sz);
-      }
+    for (int yl = ya; yl < yb; ++yl) {
+      const float wv = wrow[yl];
+      const float* q = sp + yl * (kAdjMaxCx * 3);
+      ax = fmaf(wv, q[0], ax);
+      ay = fmaf(wv, q[1], ay);
+      az = fmaf(wv, q[2], az);
     }
-    stf3(pbase + ((size_t)(czl * a.y.cm + cyl) * a.x.cm + cxl) * 3, F3{sx, sy, sz});
+    const int cz_l = czl - (k - kk);
+    stf3(pbase + ((size_t)(cz_l * a.y.cm + cyl) * a.x.cm + cxl) * 3, F3{ax, ay, az});
   }
-  // No trailing barrier: the next emit's first barrier orders these LDS reads
-  // before its Sx writes.  The entries (read before the second barrier) share
-  // each wave's region with the next plane's tile rows, which the wave writes
-  // only after that barrier.
 }
 
 // One step of the x-moments: voxel o of the tile row with value d.
@@ -207,8 +226,6 @@ __device__ __forceinline__ void adj_xmoment_step(int o, const float* __restrict_
 // the wave's kAdjRowsPerWave rows x (kAdjTilesX * DX) voxels, enumerated
 // v = row * kAdjTilesX * DX + x; lane j loads v = k * 64 + j (k < DX), i.e.
 // consecutive lanes read consecutive 12-byte voxels.
-constexpr int kAdjRowsPerWave = kWave / kAdjTilesX;
-
 template <int DX>
 __device__ __forceinline__ void adj_plane_load(const float* __restrict__ plane, const AdjBrick& b, int nx,
                                                int ywave, int lane, F3 (&d)[DX]) {
@@ -280,23 +297,32 @@ __device__ __forceinline__ void adj_xmoments_generic(const float* __restrict__ r
 template <int DX>
 __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, float* __restrict__ part,
                                           const AdjGeom& a, const float* __restrict__ lut, int brick,
-                                          AdjSmem& sm, int tid) {
+                                          AdjSmem<DX>& sm, int tid) {
   const VolGeom& g = a.g;
   const int dx = DX > 0 ? DX : g.dx;
   const AdjBrick b = adj_brick_geom(a, brick);
   float* pbase = part + (size_t)brick * a.z.cm * a.y.cm * a.x.cm * 3;
 
-  __syncthreads();  // a previous brick of this workgroup may still read WY
-  for (int i = tid; i < kAdjMaxY * 4; i += kAdjThreads) {
-    const int y = b.y0 + (i >> 2);
+  __syncthreads();  // a previous brick of this workgroup may still read the tables
+  // Window row cyl (cy = cy0 + cyl) collects brick rows y with
+  // cy - 3 <= floor(y/dy) <= cy, a contiguous range; weight By_{cy - floor(y/dy)}.
+  for (int i = tid; i < b.Cy * kAdjMaxY; i += kAdjThreads) {
+    const int cyl = i / kAdjMaxY, yl = i - cyl * kAdjMaxY;
+    const int y = b.y0 + yl;
     float wv = 0.f;
     if (y < b.ye) {
       const int t = y / g.dy;
-      wv = lut_row(lut, g.dy, y - t * g.dy)[i & 3];
+      const int m = b.cy0 + cyl - t;
+      if (m >= 0 && m < 4) wv = lut_row(lut, g.dy, y - t * g.dy)[m];
     }
-    sm.WY[i] = wv;
+    sm.WYC[i] = wv;
   }
-  // (the first adj_emit barrier orders these writes before any read)
+  for (int cyl = tid; cyl < b.Cy; cyl += kAdjThreads) {
+    const int cy = b.cy0 + cyl;
+    sm.YR[2 * cyl] = max(max(0, (cy - 3) * g.dy), b.y0) - b.y0;
+    sm.YR[2 * cyl + 1] = max(min((cy + 1) * g.dy, b.ye) - b.y0, sm.YR[2 * cyl]);
+  }
+  // (the first y-contraction's barrier orders these writes before any read)
 
   const int txl = tid % kAdjTilesX;
   const int yl = tid / kAdjTilesX;
@@ -319,7 +345,7 @@ __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, floa
   int oz = b.z0 - tz * g.dz;
   const int lane = tid & (kWave - 1);
   const int ywave = b.y0 + (tid / kWave) * kAdjRowsPerWave;
-  float* wbuf = sm.T + (tid / kWave) * kAdjWaveBuf;
+  float* wbuf = sm.T + (tid / kWave) * adj_wave_buf(DX);
   const float* plane0 = dfield + (size_t)b.z0 * zs;
 
   // One voxel plane: x-moments of this lane's tile row, z-accumulation, and the
@@ -340,7 +366,7 @@ __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, floa
       F3 fin[4];
 #pragma unroll
       for (int l = 0; l < 4; ++l) fin[l] = acc[0][l];
-      adj_emit(a, b, pbase, sm, tid, tz - b.cz0, fin);
+      adj_emit<DX>(a, b, pbase, sm, tid, tz - b.cz0, tz - b.cz0, false, fin);
 #pragma unroll
       for (int l = 0; l < 4; ++l) {
         acc[0][l] = acc[1][l];
@@ -375,13 +401,20 @@ __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, floa
       step(M, z);
     }
   }
-  // The last tile's four planes (the last three are shared with the next brick).
-#pragma unroll
+  // The last tile's four planes (the last three are shared with the next brick),
+  // shifted through acc[0] so the emission is instantiated once more, not four times.
+#pragma unroll 1
   for (int n = 0; n < 4; ++n) {
     F3 fin[4];
 #pragma unroll
-    for (int l = 0; l < 4; ++l) fin[l] = acc[n][l];
-    adj_emit(a, b, pbase, sm, tid, tz - b.cz0 + n, fin);
+    for (int l = 0; l < 4; ++l) fin[l] = acc[0][l];
+    adj_emit<DX>(a, b, pbase, sm, tid, tz - b.cz0 + n, tz - b.cz0 + n, n == 3, fin);
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      acc[0][l] = acc[1][l];
+      acc[1][l] = acc[2][l];
+      acc[2][l] = acc[3][l];
+    }
   }
 }
 

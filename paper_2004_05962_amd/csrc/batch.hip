@@ -117,7 +117,7 @@ template <int DX>
 __global__ __launch_bounds__(kAdjThreads) void batch_adj1_kernel(const VolDesc* __restrict__ vols, int count,
                                                                   int64_t total, int chunked,
                                                                   const float* __restrict__ lut) {
-  __shared__ AdjSmem sm;
+  __shared__ AdjSmem<DX> sm;
   const Slice s = make_slice(total, chunked);
   for (int64_t item = s.begin; item < s.end; item += s.step) {
     const int vi = uniform(find_volume(vols, count, item, kAdj1));
