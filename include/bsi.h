@@ -91,6 +91,25 @@ int32_t bsi_adjoint(const float* dfield, const int32_t dims[3], const int32_t sp
                     float* grid_grad, void* workspace, size_t workspace_bytes,
                     hipStream_t stream);
 
+/* The two passes of bsi_adjoint as separate calls; bsi_adjoint is exactly
+   bsi_adjoint_partials followed by bsi_adjoint_reduce on the same workspace and
+   stream, with identical bits.  Splitting them lets a caller time or overlap
+   the passes, or reduce partials written earlier.
+   bsi_adjoint_partials: reads dfield and writes, for every brick of voxels, the
+   partial sums of that brick's voxels to each control point it touches into
+   workspace (layout internal to the library).
+   bsi_adjoint_reduce: sums each control point's brick partials in a fixed order
+   and OVERWRITES grid_grad.  The workspace must hold the output of a
+   bsi_adjoint_partials call of the same geometry that is ordered before it
+   (same stream, or synchronised).
+   Arguments, ownership and errors as in bsi_adjoint. */
+int32_t bsi_adjoint_partials(const float* dfield, const int32_t dims[3],
+                             const int32_t spacing[3], void* workspace,
+                             size_t workspace_bytes, hipStream_t stream);
+int32_t bsi_adjoint_reduce(const void* workspace, size_t workspace_bytes,
+                           const int32_t dims[3], const int32_t spacing[3],
+                           float* grid_grad, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * SSD registration step (the FFD loop of Sec. 6 with a sum-of-squared-
  * differences similarity standing in for the paper's NiftyReg measure).

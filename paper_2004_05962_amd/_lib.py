@@ -26,7 +26,7 @@ BSI_MAX_SPACING = 64
 
 EXPORTS = (
     "bsi_version", "bsi_last_error", "bsi_grid_dims", "bsi_forward", "bsi_adjoint_workspace_size",
-    "bsi_adjoint", "bsi_warp", "bsi_ssd_workspace_size", "bsi_ssd_grad", "bsi_descent_step",
+    "bsi_adjoint", "bsi_adjoint_partials", "bsi_adjoint_reduce", "bsi_warp", "bsi_ssd_workspace_size", "bsi_ssd_grad", "bsi_descent_step",
     "bsi_batch_create", "bsi_batch_bind", "bsi_batch_tune", "bsi_batch_config", "bsi_batch_run",
     "bsi_batch_run_separate", "bsi_batch_capture", "bsi_batch_launch", "bsi_batch_destroy",
 )
@@ -60,6 +60,8 @@ def lib():
         "bsi_forward": ([_VP, p3, p3, _VP, _VP], i32),
         "bsi_adjoint_workspace_size": ([p3, p3, ctypes.POINTER(sz)], i32),
         "bsi_adjoint": ([_VP, p3, p3, _VP, _VP, sz, _VP], i32),
+        "bsi_adjoint_partials": ([_VP, p3, p3, _VP, sz, _VP], i32),
+        "bsi_adjoint_reduce": ([_VP, sz, p3, p3, _VP, _VP], i32),
         "bsi_warp": ([_VP, _VP, p3, _VP, _VP], i32),
         "bsi_ssd_workspace_size": ([p3, ctypes.POINTER(sz)], i32),
         "bsi_ssd_grad": ([_VP, _VP, _VP, p3, _VP, _VP, _VP, sz, _VP], i32),
@@ -169,11 +171,31 @@ def bsi_adjoint(dfield, dims, spacing, grid_grad, workspace, stream=None):
     ``workspace`` is a device tensor of at least bsi_adjoint_workspace_size bytes."""
     d = _ptr(dfield, "dfield", field_shape(dims))
     g = _ptr(grid_grad, "grid_grad", grid_shape(dims, spacing))
-    if workspace.device.type != "cuda" or not workspace.is_contiguous():
+    w, nbytes = _workspace(workspace)
+    _check(lib().bsi_adjoint(d, _triple(dims, "dims"), _triple(spacing, "spacing"), g, w, nbytes,
+                             _stream(stream)))
+
+
+def bsi_adjoint_partials(dfield, dims, spacing, workspace, stream=None):
+    """Pass 1 of bsi_adjoint: per-brick partial sums of ``dfield`` into ``workspace``."""
+    d = _ptr(dfield, "dfield", field_shape(dims))
+    w, nbytes = _workspace(workspace)
+    _check(lib().bsi_adjoint_partials(d, _triple(dims, "dims"), _triple(spacing, "spacing"), w, nbytes,
+                                      _stream(stream)))
+
+
+def bsi_adjoint_reduce(workspace, dims, spacing, grid_grad, stream=None):
+    """Pass 2 of bsi_adjoint: fixed-order sum of the partials into ``grid_grad`` (overwritten)."""
+    g = _ptr(grid_grad, "grid_grad", grid_shape(dims, spacing))
+    w, nbytes = _workspace(workspace)
+    _check(lib().bsi_adjoint_reduce(w, nbytes, _triple(dims, "dims"), _triple(spacing, "spacing"), g,
+                                    _stream(stream)))
+
+
+def _workspace(workspace):
+    if not isinstance(workspace, torch.Tensor) or workspace.device.type != "cuda" or not workspace.is_contiguous():
         raise ValueError("workspace must be a contiguous device tensor")
-    nbytes = workspace.numel() * workspace.element_size()
-    _check(lib().bsi_adjoint(d, _triple(dims, "dims"), _triple(spacing, "spacing"), g, _raw(workspace),
-                             nbytes, _stream(stream)))
+    return _raw(workspace), workspace.numel() * workspace.element_size()
 
 
 # ---------------------------------------------------------------- registration

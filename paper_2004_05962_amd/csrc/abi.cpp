@@ -156,25 +156,61 @@ int32_t bsi_adjoint_workspace_size(const int32_t dims[3], const int32_t spacing[
   return BSI_OK;
 }
 
-int32_t bsi_adjoint(const float* dfield, const int32_t dims[3], const int32_t spacing[3], float* grid_grad,
-                    void* workspace, size_t workspace_bytes, hipStream_t stream) {
-  clear_error();
+namespace {
+// Geometry and workspace checks shared by the adjoint entry points.
+int32_t adjoint_setup(const int32_t dims[3], const int32_t spacing[3], const void* workspace,
+                      size_t workspace_bytes, AdjGeom* a) {
   VolGeom g;
   int32_t rc = make_geom(dims, spacing, &g);
   if (rc) return rc;
-  if (!dfield) return null_arg("dfield");
-  if (!grid_grad) return null_arg("grid_grad");
   if (!workspace) return null_arg("workspace");
-  const AdjGeom a = make_adj_geom(g);
-  const size_t need = adj_workspace_bytes(a);
+  *a = make_adj_geom(g);
+  const size_t need = adj_workspace_bytes(*a);
   if (workspace_bytes < need) {
     set_error("workspace too small: need " + std::to_string(need) + " bytes");
     return BSI_ERR_INVALID_ARG;
   }
+  return BSI_OK;
+}
+}  // namespace
+
+int32_t bsi_adjoint(const float* dfield, const int32_t dims[3], const int32_t spacing[3], float* grid_grad,
+                    void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  clear_error();
+  AdjGeom a;
+  int32_t rc = adjoint_setup(dims, spacing, workspace, workspace_bytes, &a);
+  if (rc) return rc;
+  if (!dfield) return null_arg("dfield");
+  if (!grid_grad) return null_arg("grid_grad");
   const float* lut = nullptr;
   if ((rc = device_lut(&lut))) return rc;
   hipError_t e = launch_adjoint(dfield, grid_grad, a, lut, static_cast<float*>(workspace), stream);
   return e == hipSuccess ? BSI_OK : hip_fail(e, "launching the adjoint kernels");
+}
+
+int32_t bsi_adjoint_partials(const float* dfield, const int32_t dims[3], const int32_t spacing[3],
+                             void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  clear_error();
+  AdjGeom a;
+  int32_t rc = adjoint_setup(dims, spacing, workspace, workspace_bytes, &a);
+  if (rc) return rc;
+  if (!dfield) return null_arg("dfield");
+  const float* lut = nullptr;
+  if ((rc = device_lut(&lut))) return rc;
+  hipError_t e = launch_adjoint_partials(dfield, a, lut, static_cast<float*>(workspace), stream);
+  return e == hipSuccess ? BSI_OK : hip_fail(e, "launching the adjoint partials kernel");
+}
+
+int32_t bsi_adjoint_reduce(const void* workspace, size_t workspace_bytes, const int32_t dims[3],
+                           const int32_t spacing[3], float* grid_grad, hipStream_t stream) {
+  clear_error();
+  AdjGeom a;
+  int32_t rc = adjoint_setup(dims, spacing, workspace, workspace_bytes, &a);
+  if (rc) return rc;
+  if (!grid_grad) return null_arg("grid_grad");
+  if ((rc = device_only())) return rc;
+  hipError_t e = launch_adjoint_reduce(static_cast<const float*>(workspace), grid_grad, a, stream);
+  return e == hipSuccess ? BSI_OK : hip_fail(e, "launching the adjoint reduce kernel");
 }
 
 int32_t bsi_warp(const float* field, const float* image, const int32_t dims[3], float* out,

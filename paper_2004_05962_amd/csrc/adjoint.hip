@@ -81,8 +81,8 @@ size_t adj_workspace_bytes(const AdjGeom& a) {
   return (size_t)a.x.nb * a.y.nb * a.z.nb * a.x.cm * a.y.cm * a.z.cm * 3 * sizeof(float);
 }
 
-hipError_t launch_adjoint(const float* dfield, float* grad, const AdjGeom& a, const float* lut,
-                          float* part, hipStream_t s) {
+hipError_t launch_adjoint_partials(const float* dfield, const AdjGeom& a, const float* lut, float* part,
+                                  hipStream_t s) {
   const long nbricks = (long)a.x.nb * a.y.nb * a.z.nb;
   const dim3 grid((unsigned)nbricks), block(kAdjThreads);
   switch (a.g.dx) {
@@ -96,12 +96,21 @@ hipError_t launch_adjoint(const float* dfield, float* grad, const AdjGeom& a, co
     case 8: hipLaunchKernelGGL(adj_pass1_kernel<8>, grid, block, 0, s, dfield, part, a, lut); break;
     default: hipLaunchKernelGGL(adj_pass1_kernel<0>, grid, block, 0, s, dfield, part, a, lut); break;
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_reduce(const float* part, float* grad, const AdjGeom& a, hipStream_t s) {
   const long npts = (long)a.g.gx * a.g.gy * a.g.gz;
   hipLaunchKernelGGL(adj_pass2_kernel, dim3((unsigned)((npts + kGatherThreads - 1) / kGatherThreads)),
                      dim3(kGatherThreads), 0, s, part, grad, a);
   return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const float* dfield, float* grad, const AdjGeom& a, const float* lut,
+                          float* part, hipStream_t s) {
+  hipError_t e = launch_adjoint_partials(dfield, a, lut, part, s);
+  if (e != hipSuccess) return e;
+  return launch_adjoint_reduce(part, grad, a, s);
 }
 
 }  // namespace bsi

@@ -41,6 +41,9 @@ hipError_t launch_forward(const float* grid, float* field, const VolGeom& g, con
                           hipStream_t s);
 hipError_t launch_adjoint(const float* dfield, float* grad, const AdjGeom& a, const float* lut,
                           float* part, hipStream_t s);
+hipError_t launch_adjoint_partials(const float* dfield, const AdjGeom& a, const float* lut, float* part,
+                                  hipStream_t s);
+hipError_t launch_adjoint_reduce(const float* part, float* grad, const AdjGeom& a, hipStream_t s);
 hipError_t launch_warp(const float* field, const float* image, const VolGeom& g, float* out,
                        hipStream_t s);
 size_t ssd_partial_count(const VolGeom& g);

@@ -80,6 +80,10 @@ def test_null_pointers_rejected_before_device():
     assert _call("bsi_forward", NULL, d, s, P, NULL) == _lib.BSI_ERR_INVALID_ARG
     assert _call("bsi_forward", P, d, s, NULL, NULL) == _lib.BSI_ERR_INVALID_ARG
     assert _call("bsi_adjoint", P, d, s, P, NULL, 1 << 30, NULL) == _lib.BSI_ERR_INVALID_ARG
+    assert _call("bsi_adjoint_partials", NULL, d, s, P, 1 << 30, NULL) == _lib.BSI_ERR_INVALID_ARG
+    assert _call("bsi_adjoint_partials", P, d, s, NULL, 1 << 30, NULL) == _lib.BSI_ERR_INVALID_ARG
+    assert _call("bsi_adjoint_reduce", P, 1 << 30, d, s, NULL, NULL) == _lib.BSI_ERR_INVALID_ARG
+    assert _call("bsi_adjoint_reduce", NULL, 1 << 30, d, s, P, NULL) == _lib.BSI_ERR_INVALID_ARG
     assert _call("bsi_warp", NULL, P, d, P, NULL) == _lib.BSI_ERR_INVALID_ARG
     assert _call("bsi_ssd_grad", P, P, P, d, P, NULL, P, 1 << 30, NULL) == _lib.BSI_ERR_INVALID_ARG
     assert _call("bsi_descent_step", NULL, P, ctypes.c_float(1.0), 4, NULL) == _lib.BSI_ERR_INVALID_ARG
@@ -93,6 +97,8 @@ def test_workspace_size_checked_before_device():
     assert need > 0
     assert _call("bsi_adjoint", P, d, s, P, P, need - 1, NULL) == _lib.BSI_ERR_INVALID_ARG
     assert "workspace too small" in bsi.bsi_last_error()
+    assert _call("bsi_adjoint_partials", P, d, s, P, need - 1, NULL) == _lib.BSI_ERR_INVALID_ARG
+    assert _call("bsi_adjoint_reduce", P, need - 1, d, s, P, NULL) == _lib.BSI_ERR_INVALID_ARG
     ssd = bsi.bsi_ssd_workspace_size((40, 30, 20))
     assert _call("bsi_ssd_grad", P, P, P, d, P, P, P, ssd - 1, NULL) == _lib.BSI_ERR_INVALID_ARG
 

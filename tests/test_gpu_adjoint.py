@@ -121,3 +121,32 @@ def test_workspace_too_small_raises():
     ws = torch.empty(bsi.bsi_adjoint_workspace_size(dims, spacing) - 4, dtype=torch.uint8, device="cuda")
     with pytest.raises(bsi.BSIError):
         bsi.bsi_adjoint(d, dims, spacing, out, ws)
+
+
+@pytest.mark.parametrize("dims,spacing", [((64, 64, 64), (5, 5, 5)), ((33, 40, 129), (8, 33, 6))])
+def test_split_passes_bit_identical(dims, spacing):
+    """bsi_adjoint_partials + bsi_adjoint_reduce == bsi_adjoint, bit for bit, also
+    when the reduce runs on another stream ordered by an event."""
+    say("adjoint split passes", dims, spacing)
+    d = dev(workloads.random_field(dims, 1.0, seed=77))
+    nbytes = bsi.bsi_adjoint_workspace_size(dims, spacing)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    whole = torch.empty(bsi.grid_shape(dims, spacing), device="cuda")
+    bsi.bsi_adjoint(d, dims, spacing, whole, ws)
+    split = torch.full_like(whole, float("nan"))
+    ws2 = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    bsi.bsi_adjoint_partials(d, dims, spacing, ws2)
+    done = torch.cuda.Event()
+    done.record()
+    side = torch.cuda.Stream()
+    side.wait_event(done)
+    bsi.bsi_adjoint_reduce(ws2, dims, spacing, split, stream=side)
+    torch.cuda.synchronize()
+    assert torch.equal(whole, split)
+    ref = oracle.adjoint(host(d), dims, spacing)
+    assert max_abs(host(split), ref) <= 1e-5 * float(np.abs(ref).max())
+    small = torch.empty(nbytes - 4, dtype=torch.uint8, device="cuda")
+    with pytest.raises(bsi.BSIError):
+        bsi.bsi_adjoint_partials(d, dims, spacing, small)
+    with pytest.raises(bsi.BSIError):
+        bsi.bsi_adjoint_reduce(small, dims, spacing, split)
