@@ -11,10 +11,13 @@
 // with weights that are the same for every lane, then accumulates them into
 // the four control planes the current z-tile touches,
 //   A[n][l] += Bz_n(w) * M_l                                  (n = cz - tz).
-// When a z-tile ends, plane A[0] is finished; the workgroup combines it in LDS
-//   Sx[y][cx] = sum_l A[0][l] of tile (cx - l)
-//   G[cy][cx] = sum_m sum_{y in tile cy-m} By_m(v(y)) * Sx[y][cx]
-// and writes G, the brick's partial gradient of that control plane.  Every
+// When a z-tile ends, plane A[0] is finished.  Each wave combines its own rows
+// over x in its private LDS region (no workgroup barrier),
+//   Sx[y][cx] = sum_l A[0][l] of tile (cx - l),
+// and after every second finished plane the workgroup contracts the buffered
+// pair over y (one barrier per pair),
+//   G[cy][cx] = sum_m sum_{y in tile cy-m} By_m(v(y)) * Sx[y][cx],
+// and writes G, the brick's partial gradient of those control planes.  Every
 // brick writes its whole window of (cz, cy, cx) partials to the workspace.
 //
 // Pass 2 (one thread per control point) sums the partials of the bricks whose
