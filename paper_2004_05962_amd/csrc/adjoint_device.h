@@ -8,15 +8,18 @@
 // rows per wave) and marches along z.  At every voxel plane it loads the tile
 // row's dx voxels (contiguous) and forms the four x-moments
 //   M_l = sum_o Bx_l(o) * dfield[z][y][tx*dx + o]          (l = 0..3)
-// with weights that are the same for every lane, then accumulates them into
-// the four control planes the current z-tile touches,
-//   A[n][l] += Bz_n(w) * M_l                                  (n = cz - tz).
-// When a z-tile ends, plane A[0] is finished.  Each wave combines its own rows
-// over x in its private LDS region (no workgroup barrier),
-//   Sx[y][cx] = sum_l A[0][l] of tile (cx - l),
-// and after every second finished plane the workgroup contracts the buffered
-// pair over y (one barrier per pair),
-//   G[cy][cx] = sum_m sum_{y in tile cy-m} By_m(v(y)) * Sx[y][cx],
+// with weights that are the same for every lane.  The 16 lanes of a row hold
+// the brick's 16 x-tiles, so the x-contraction of the plane row is finished
+// right there, with row rotations across lanes (DPP):
+//   S[cx] = sum_l M_l of tile (cx - l)                         (l ascending)
+// lane t forms column t and, for t < 3, column 16 + t (the columns past the
+// last tile).  These two columns are accumulated into the four control planes
+// the current z-tile touches,
+//   A[n] += Bz_n(w) * S                                        (n = cz - tz).
+// When a z-tile ends, plane A[0] is finished and goes to an LDS slot; after
+// every second finished plane the workgroup contracts the buffered pair over y
+// (one barrier per pair),
+//   G[cy][cx] = sum_m sum_{y in tile cy-m} By_m(v(y)) * A[0][y][cx],
 // and writes G, the brick's partial gradient of those control planes.  Every
 // brick writes its whole window of (cz, cy, cx) partials to the workspace.
 //
@@ -59,19 +62,17 @@ constexpr int kAdjRowsPerWave = kWave / kAdjTilesX;  // a wave holds whole rows 
 constexpr int kAdjSlotsX = 4;  // x-combined planes buffered in LDS (two pairs)
 
 // Per-wave LDS region: the wave's tile rows of one voxel plane (64 * DX voxels)
-// on their way from coalesced loads to tile-owning lanes; between planes it
-// also holds the wave's finished-plane entries (12 floats per lane).  Each
-// wave only ever touches its own region.
-__host__ __device__ constexpr int adj_wave_buf(int dx) {
-  return (kWave * dx * 3 > kWave * 12) ? kWave * dx * 3 : kWave * 12;
-}
+// on their way from coalesced loads to tile-owning lanes.  Each wave only ever
+// touches its own region.  The generic path (DX == 0) reads global memory
+// directly and needs none.
+__host__ __device__ constexpr int adj_wave_buf(int dx) { return dx > 0 ? kWave * dx * 3 : 1; }
 
 constexpr int kAdjMaxCy = kAdjMaxY + 4;  // y-window bound (32 one-row units)
 
 template <int DX>
 struct AdjSmem {
-  float T[kAdjWaves * adj_wave_buf(DX)];              // per-wave transpose buffer / entries
-  float Sx[kAdjSlotsX * kAdjMaxY * kAdjMaxCx * 3];     // x-combined planes
+  float T[kAdjWaves * adj_wave_buf(DX)];              // per-wave transpose buffers
+  float Sx[kAdjSlotsX * kAdjMaxY * kAdjMaxCx * 3];     // finished planes, x-contracted
   float WYC[kAdjMaxCy * kAdjMaxY];                    // By weight of brick row y for window row cy
   int YR[kAdjMaxCy * 2];                              // rows [ya, yb) of the brick in cy's support
 };
@@ -118,11 +119,10 @@ __device__ __forceinline__ AdjBrick adj_brick_geom(const AdjGeom& a, int brick) 
 }
 
 // Finished control plane number k of the brick (czl = cz - cz0).  Collective:
-// every thread of the workgroup calls it.  v[l] = A[0][l] of this thread's
-// (row, tile); zero for idle threads.
-//  1. Each wave combines its own rows over x (its 4 rows hold all 16 tiles):
-//       Sx[y][cx] = sum over l of A[0][l] of tile cx - l   (l ascending)
-//     through its own LDS region, with no workgroup barrier, into slot k % 4.
+// every thread of the workgroup calls it with its (row, column) values of
+// A[0]: cm for column txl, cw for column 16 + txl (lanes txl < 3); zero for
+// idle threads.
+//  1. Every thread writes its columns of the plane into LDS slot k % 4.
 //  2. After every second plane (and after the brick's last one) one barrier,
 //     then the y-contraction of the buffered planes, over the brick rows in
 //     cy's support in ascending order:
@@ -132,47 +132,16 @@ __device__ __forceinline__ AdjBrick adj_brick_geom(const AdjGeom& a, int brick) 
 // pair k + 2, k + 3, which every thread passes after its y-contraction of k.
 template <int DX>
 __device__ __forceinline__ void adj_emit(const AdjGeom& a, const AdjBrick& b, float* __restrict__ pbase,
-                                         AdjSmem<DX>& sm, int tid, int k, int czl, bool last,
-                                         const F3 (&v)[4]) {
-  const int lane = tid & (kWave - 1);
-  const int wave = tid / kWave;
-  float* wbuf = sm.T + wave * adj_wave_buf(DX);
-  wave_lds_sync();  // this wave's reads of its region (the plane's tile rows) come first
+                                         AdjSmem<DX>& sm, int tid, int k, int czl, bool last, const F3& cm,
+                                         const F3& cw) {
   {
-    float* e = wbuf + lane * 12;
-#pragma unroll
-    for (int l = 0; l < 4; ++l) {
-      e[3 * l] = v[l].x;
-      e[3 * l + 1] = v[l].y;
-      e[3 * l + 2] = v[l].z;
+    const int txl = tid % kAdjTilesX;
+    const int yl = tid / kAdjTilesX;
+    float* row = sm.Sx + (k % kAdjSlotsX) * (kAdjMaxY * kAdjMaxCx * 3) + yl * (kAdjMaxCx * 3);
+    if (yl < b.ye - b.y0) {
+      if (txl < b.Cx) stf3(row + txl * 3, cm);
+      if (txl < 3 && kAdjTilesX + txl < b.Cx) stf3(row + (kAdjTilesX + txl) * 3, cw);
     }
-  }
-  wave_lds_sync();
-  float* sx = sm.Sx + (k % kAdjSlotsX) * (kAdjMaxY * kAdjMaxCx * 3);
-  const int rows = b.ye - b.y0;
-  // lane -> (row r, window column cxl): columns 0..15 for all 4 rows, then the
-  // 3 columns past the last tile (lanes 0..11)
-#pragma unroll 1
-  for (int pass = 0; pass < 2; ++pass) {
-    const int r = pass == 0 ? lane / kAdjTilesX : lane / 3;
-    const int cxl = pass == 0 ? lane % kAdjTilesX : kAdjTilesX + lane % 3;
-    const int yl = wave * kAdjRowsPerWave + r;
-    if ((pass == 1 && lane >= 3 * kAdjRowsPerWave) || cxl >= b.Cx || yl >= rows) continue;
-    float ax = 0.f, ay = 0.f, az = 0.f;
-#pragma unroll
-    for (int l = 0; l < 4; ++l) {
-      const int txl = cxl - l;
-      if (txl >= 0 && txl < b.ntx) {
-        const float* e = wbuf + (r * kAdjTilesX + txl) * 12 + l * 3;
-        ax += e[0];
-        ay += e[1];
-        az += e[2];
-      }
-    }
-    float* o = sx + (yl * kAdjMaxCx + cxl) * 3;
-    o[0] = ax;
-    o[1] = ay;
-    o[2] = az;
   }
   if (!(k & 1) && !last) return;  // the y-contraction waits for the pair
 
@@ -201,6 +170,39 @@ __device__ __forceinline__ void adj_emit(const AdjGeom& a, const AdjBrick& b, fl
     const int cz_l = czl - (k - kk);
     stf3(pbase + ((size_t)(cz_l * a.y.cm + cyl) * a.x.cm + cxl) * 3, F3{ax, ay, az});
   }
+}
+
+// Value of lane (i - N) mod 16 of this lane's row of 16 lanes (DPP row_ror).
+template <int N>
+__device__ __forceinline__ float row_ror(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x120 + N, 0xF, 0xF, false));
+}
+
+template <int L>
+__device__ __forceinline__ void adj_xcombine_term(int txl, const F3& m, F3& cm, F3& cw) {
+  const F3 r{row_ror<L>(m.x), row_ror<L>(m.y), row_ror<L>(m.z)};  // M_L of tile txl - L (mod 16)
+  if (txl >= L) {
+    cm.x += r.x;
+    cm.y += r.y;
+    cm.z += r.z;
+  } else {
+    cw.x += r.x;
+    cw.y += r.y;
+    cw.z += r.z;
+  }
+}
+
+// x-contraction of one plane row across the 16 tile lanes of a row:
+//   cm = S[txl]      = sum_{l <= txl} M_l(tile txl - l)
+//   cw = S[16 + txl] = sum_{l > txl}  M_l(tile 16 + txl - l)   (txl < 3)
+// l ascending.  Idle lanes hold M = 0, so columns past the brick's last tile
+// come out right.  Every lane of the wave takes part (no lane may be inactive).
+__device__ __forceinline__ void adj_xcombine(int txl, const F3 (&M)[4], F3& cm, F3& cw) {
+  cm = M[0];
+  cw = F3{0.f, 0.f, 0.f};
+  adj_xcombine_term<1>(txl, M[1], cm, cw);
+  adj_xcombine_term<2>(txl, M[2], cm, cw);
+  adj_xcombine_term<3>(txl, M[3], cm, cw);
 }
 
 // One step of the x-moments: voxel o of the tile row with value d.
@@ -338,11 +340,9 @@ __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, floa
   const float* src = dfield + (((size_t)b.z0 * g.ny + (act ? y : 0)) * g.nx + (act ? x : 0)) * 3;
   const float* lutx = lut_row(lut, dx, 0);
 
-  F3 acc[4][4];  // [n][l]
+  F3 acc[4], accw[4];  // columns txl and 16 + txl of control planes tz + n
 #pragma unroll
-  for (int n = 0; n < 4; ++n)
-#pragma unroll
-    for (int l = 0; l < 4; ++l) acc[n][l] = F3{0.f, 0.f, 0.f};
+  for (int n = 0; n < 4; ++n) acc[n] = accw[n] = F3{0.f, 0.f, 0.f};
 
   int tz = b.cz0;
   int oz = b.z0 - tz * g.dz;
@@ -353,30 +353,28 @@ __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, floa
 
   // One voxel plane: x-moments of this lane's tile row, z-accumulation, and the
   // emission of the finished control plane when a z-tile ends.
-  auto step = [&](const F3* M, int z) {
+  auto step = [&](const F3 (&M)[4], int z) {
+    F3 cm, cw;
+    adj_xcombine(txl, M, cm, cw);
     const float* wz = lut_row(lut, g.dz, oz);
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
       const float w = wz[n];
-#pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        acc[n][l].x = fmaf(w, M[l].x, acc[n][l].x);
-        acc[n][l].y = fmaf(w, M[l].y, acc[n][l].y);
-        acc[n][l].z = fmaf(w, M[l].z, acc[n][l].z);
-      }
+      acc[n].x = fmaf(w, cm.x, acc[n].x);
+      acc[n].y = fmaf(w, cm.y, acc[n].y);
+      acc[n].z = fmaf(w, cm.z, acc[n].z);
+      accw[n].x = fmaf(w, cw.x, accw[n].x);
+      accw[n].y = fmaf(w, cw.y, accw[n].y);
+      accw[n].z = fmaf(w, cw.z, accw[n].z);
     }
     if (++oz == g.dz && z + 1 < b.ze) {
-      F3 fin[4];
+      adj_emit<DX>(a, b, pbase, sm, tid, tz - b.cz0, tz - b.cz0, false, acc[0], accw[0]);
 #pragma unroll
-      for (int l = 0; l < 4; ++l) fin[l] = acc[0][l];
-      adj_emit<DX>(a, b, pbase, sm, tid, tz - b.cz0, tz - b.cz0, false, fin);
-#pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        acc[0][l] = acc[1][l];
-        acc[1][l] = acc[2][l];
-        acc[2][l] = acc[3][l];
-        acc[3][l] = F3{0.f, 0.f, 0.f};
+      for (int n = 0; n < 3; ++n) {
+        acc[n] = acc[n + 1];
+        accw[n] = accw[n + 1];
       }
+      acc[3] = accw[3] = F3{0.f, 0.f, 0.f};
       oz = 0;
       ++tz;
     }
@@ -408,15 +406,11 @@ __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, floa
   // shifted through acc[0] so the emission is instantiated once more, not four times.
 #pragma unroll 1
   for (int n = 0; n < 4; ++n) {
-    F3 fin[4];
+    adj_emit<DX>(a, b, pbase, sm, tid, tz - b.cz0 + n, tz - b.cz0 + n, n == 3, acc[0], accw[0]);
 #pragma unroll
-    for (int l = 0; l < 4; ++l) fin[l] = acc[0][l];
-    adj_emit<DX>(a, b, pbase, sm, tid, tz - b.cz0 + n, tz - b.cz0 + n, n == 3, fin);
-#pragma unroll
-    for (int l = 0; l < 4; ++l) {
-      acc[0][l] = acc[1][l];
-      acc[1][l] = acc[2][l];
-      acc[2][l] = acc[3][l];
+    for (int j = 0; j < 3; ++j) {
+      acc[j] = acc[j + 1];
+      accw[j] = accw[j + 1];
     }
   }
 }

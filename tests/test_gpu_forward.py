@@ -59,6 +59,25 @@ def test_forward_canary_and_rerun_bits():
     assert torch.equal(field, again)
 
 
+@pytest.mark.parametrize("shift", [1, 2, 3])
+@pytest.mark.parametrize("dims", [(77, 45, 31), (128, 8, 6)])
+def test_forward_unaligned_field_pointer(shift, dims):
+    """A field that starts 4, 8 or 12 bytes past a 16-byte boundary: the same
+    bits as an aligned field, and nothing written outside it."""
+    spacing = (5, 4, 6)
+    say("forward unaligned field", dims, spacing, shift)
+    grid = dev(workloads.random_grid(dims, spacing, 2.0, seed=6))
+    n = int(np.prod(bsi.field_shape(dims)))
+    buf = torch.full((n + 64,), 1.0e30, dtype=torch.float32, device="cuda")
+    field = buf[shift:shift + n].view(bsi.field_shape(dims))
+    assert field.data_ptr() % 16 == 4 * shift
+    bsi.forward(grid, dims, spacing, out=field)
+    aligned = bsi.forward(grid, dims, spacing)
+    torch.cuda.synchronize()
+    assert torch.all(buf[:shift] == 1.0e30) and torch.all(buf[shift + n:] == 1.0e30)
+    assert torch.equal(field, aligned)
+
+
 @pytest.mark.parametrize("delta", workloads.CFG2_SPACINGS)
 def test_forward_clinical_size_sampled(delta):
     case = workloads.cfg2(delta)
