@@ -17,7 +17,8 @@ Printed as ONE JSON line on stdout (logs go to stderr), with:
   extras        forward at spacings 3 and 8, the adjoint alone at 256^3
                 (MALL flushed between repetitions), the 32-volume batched
                 graph launch against per-volume launches, and one SSD
-                registration iteration at 256 x 256 x 160.
+                registration iteration at 256 x 256 x 160, fused (one pass,
+                no field in memory) and unfused (forward, SSD, adjoint).
 """
 import argparse
 import hashlib
@@ -310,14 +311,17 @@ def run_extras(torch, bsi, workloads):
     Ttrue = bsi.forward(torch.from_numpy(c["grid_true"]).cuda(), dims, sp)
     moving = torch.empty_like(fixed)
     bsi.bsi_warp(Ttrue, fixed, dims, moving)
-    reg = bsi.SSDRegistration(fixed, moving, sp, max_steps=64)
-    reg.auto_eta()
-    reg.run(3)
-    ms = median(time_events(torch, reg.step, 20))
     V = dims[0] * dims[1] * dims[2]
-    ex["registration_iteration_256x256x160_d5"] = {"ms": round(ms, 4), "gvoxel_s": round(V / ms / 1e6, 2),
-                                                   "loss_first": float(reg.losses[0]), "loss_last": float(reg.losses[reg.step_index - 1])}
-    log("registration:", ex["registration_iteration_256x256x160_d5"])
+    for fused in (True, False):
+        reg = bsi.SSDRegistration(fixed, moving, sp, max_steps=64, fused=fused)
+        reg.auto_eta()
+        reg.run(3)
+        ms = median(time_events(torch, reg.step, 20))
+        key = "registration_iteration_256x256x160_d5_" + ("fused" if fused else "unfused")
+        ex[key] = {"ms": round(ms, 4), "gvoxel_s": round(V / ms / 1e6, 2), "loss_first": float(reg.losses[0]),
+                   "loss_last": float(reg.losses[reg.step_index - 1])}
+        log("registration:", key, ex[key])
+        del reg
     return ex
 
 

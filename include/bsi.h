@@ -137,6 +137,30 @@ int32_t bsi_ssd_grad(const float* field, const float* moving, const float* fixed
                      const int32_t dims[3], float* dfield, float* loss, void* workspace,
                      size_t workspace_bytes, hipStream_t stream);
 
+/* Scratch size in bytes that bsi_ssd_fused needs for this geometry (host-only). */
+int32_t bsi_ssd_fused_workspace_size(const int32_t dims[3], const int32_t spacing[3],
+                                     size_t* bytes);
+
+/* The registration step's loss and control-grid gradient in one pass, without
+   materialising the field or its gradient (merging FFD steps into BSI, the
+   further work named in Sec. 8):
+     T = Eq. 1 of grid,  W = moving(x + T(x)),  r = W - fixed,
+     loss[0]   = sum_x r^2 (FP32, fixed order),
+     grid_grad = B^T [2 r dW/dp]  (the adjoint of Eq. 1 applied to the
+                 bsi_ssd_grad field gradient), OVERWRITTEN.
+   The result equals bsi_forward -> bsi_ssd_grad -> bsi_adjoint up to FP32
+   rounding: T is summed in another order, so a sample coordinate within
+   rounding of a cell boundary can fall in the neighbouring cell.
+   grid: [gz][gy][gx][3]; moving, fixed: [nz][ny][nx]; grid_grad as grid;
+   loss: one device float.  workspace: device scratch of at least
+   bsi_ssd_fused_workspace_size() bytes, owned by the caller, not shared by
+   concurrent calls.  Deterministic, no atomics.
+   Errors: INVALID_ARG, UNSUPPORTED, NO_DEVICE, HIP. */
+int32_t bsi_ssd_fused(const float* grid, const float* moving, const float* fixed,
+                      const int32_t dims[3], const int32_t spacing[3], float* grid_grad,
+                      float* loss, void* workspace, size_t workspace_bytes,
+                      hipStream_t stream);
+
 /* Gradient-descent update grid[i] -= eta * grad[i] for i < count (count = number
    of floats).  Errors: INVALID_ARG, NO_DEVICE, HIP. */
 int32_t bsi_descent_step(float* grid, const float* grad, float eta, int64_t count,

@@ -26,7 +26,8 @@ BSI_MAX_SPACING = 64
 
 EXPORTS = (
     "bsi_version", "bsi_last_error", "bsi_grid_dims", "bsi_forward", "bsi_adjoint_workspace_size",
-    "bsi_adjoint", "bsi_adjoint_partials", "bsi_adjoint_reduce", "bsi_warp", "bsi_ssd_workspace_size", "bsi_ssd_grad", "bsi_descent_step",
+    "bsi_adjoint", "bsi_adjoint_partials", "bsi_adjoint_reduce", "bsi_warp", "bsi_ssd_workspace_size", "bsi_ssd_grad", "bsi_ssd_fused_workspace_size", "bsi_ssd_fused",
+    "bsi_descent_step",
     "bsi_batch_create", "bsi_batch_bind", "bsi_batch_tune", "bsi_batch_config", "bsi_batch_run",
     "bsi_batch_run_separate", "bsi_batch_capture", "bsi_batch_launch", "bsi_batch_destroy",
 )
@@ -65,6 +66,8 @@ def lib():
         "bsi_warp": ([_VP, _VP, p3, _VP, _VP], i32),
         "bsi_ssd_workspace_size": ([p3, ctypes.POINTER(sz)], i32),
         "bsi_ssd_grad": ([_VP, _VP, _VP, p3, _VP, _VP, _VP, sz, _VP], i32),
+        "bsi_ssd_fused_workspace_size": ([p3, p3, ctypes.POINTER(sz)], i32),
+        "bsi_ssd_fused": ([_VP, _VP, _VP, p3, p3, _VP, _VP, _VP, sz, _VP], i32),
         "bsi_descent_step": ([_VP, _VP, ctypes.c_float, i64, _VP], i32),
         "bsi_batch_create": ([i32, p3, p3, ctypes.POINTER(_VP)], i32),
         "bsi_batch_bind": ([_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP),
@@ -222,6 +225,25 @@ def bsi_ssd_grad(field, moving, fixed, dims, dfield, loss, workspace, stream=Non
     l = _ptr(loss, "loss", (1,))
     nbytes = workspace.numel() * workspace.element_size()
     _check(lib().bsi_ssd_grad(f, m, x, _triple(dims, "dims"), d, l, _raw(workspace), nbytes, _stream(stream)))
+
+
+def bsi_ssd_fused_workspace_size(dims, spacing):
+    n = ctypes.c_size_t()
+    _check(lib().bsi_ssd_fused_workspace_size(_triple(dims, "dims"), _triple(spacing, "spacing"), ctypes.byref(n)))
+    return int(n.value)
+
+
+def bsi_ssd_fused(grid, moving, fixed, dims, spacing, grid_grad, loss, workspace, stream=None):
+    """Loss and control-grid gradient of the SSD step in one pass (field never stored)."""
+    nx, ny, nz = (int(v) for v in dims)
+    g = _ptr(grid, "grid", grid_shape(dims, spacing))
+    m = _ptr(moving, "moving", (nz, ny, nx))
+    x = _ptr(fixed, "fixed", (nz, ny, nx))
+    o = _ptr(grid_grad, "grid_grad", grid_shape(dims, spacing))
+    l = _ptr(loss, "loss", (1,))
+    w, nbytes = _workspace(workspace)
+    _check(lib().bsi_ssd_fused(g, m, x, _triple(dims, "dims"), _triple(spacing, "spacing"), o, l, w, nbytes,
+                               _stream(stream)))
 
 
 def bsi_descent_step(grid, grad, eta, stream=None):

@@ -69,12 +69,17 @@ __host__ __device__ constexpr int adj_wave_buf(int dx) { return dx > 0 ? kWave *
 
 constexpr int kAdjMaxCy = kAdjMaxY + 4;  // y-window bound (32 one-row units)
 
-template <int DX>
-struct AdjSmem {
-  float T[kAdjWaves * adj_wave_buf(DX)];              // per-wave transpose buffers
+// LDS of the emission (finished control planes and the brick's y tables).
+struct AdjEmitSmem {
   float Sx[kAdjSlotsX * kAdjMaxY * kAdjMaxCx * 3];     // finished planes, x-contracted
   float WYC[kAdjMaxCy * kAdjMaxY];                    // By weight of brick row y for window row cy
   int YR[kAdjMaxCy * 2];                              // rows [ya, yb) of the brick in cy's support
+};
+
+template <int DX>
+struct AdjSmem {
+  float T[kAdjWaves * adj_wave_buf(DX)];              // per-wave transpose buffers
+  AdjEmitSmem e;
 };
 
 
@@ -130,9 +135,8 @@ __device__ __forceinline__ AdjBrick adj_brick_geom(const AdjGeom& a, int brick) 
 //     written to the brick's partials.
 // Slot reuse: plane k + 4 overwrites slot k % 4 only after the barrier of the
 // pair k + 2, k + 3, which every thread passes after its y-contraction of k.
-template <int DX>
 __device__ __forceinline__ void adj_emit(const AdjGeom& a, const AdjBrick& b, float* __restrict__ pbase,
-                                         AdjSmem<DX>& sm, int tid, int k, int czl, bool last, const F3& cm,
+                                         AdjEmitSmem& sm, int tid, int k, int czl, bool last, const F3& cm,
                                          const F3& cw) {
   {
     const int txl = tid % kAdjTilesX;
@@ -298,16 +302,12 @@ __device__ __forceinline__ void adj_xmoments_generic(const float* __restrict__ r
   }
 }
 
-// Pass 1 for one brick.  Collective over the workgroup (kAdjThreads threads).
-template <int DX>
-__device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, float* __restrict__ part,
-                                          const AdjGeom& a, const float* __restrict__ lut, int brick,
-                                          AdjSmem<DX>& sm, int tid) {
+// Per-brick y tables of the emission: WYC[cyl][yl] = By weight of brick row yl
+// for window row cyl (0 outside cy's support), YR[cyl] = the support's rows.
+// Collective; the first y-contraction's barrier orders these writes before any read.
+__device__ __forceinline__ void adj_tables(const AdjGeom& a, const AdjBrick& b, const float* __restrict__ lut,
+                                           AdjEmitSmem& sm, int tid) {
   const VolGeom& g = a.g;
-  const int dx = DX > 0 ? DX : g.dx;
-  const AdjBrick b = adj_brick_geom(a, brick);
-  float* pbase = part + (size_t)brick * a.z.cm * a.y.cm * a.x.cm * 3;
-
   __syncthreads();  // a previous brick of this workgroup may still read the tables
   // Window row cyl (cy = cy0 + cyl) collects brick rows y with
   // cy - 3 <= floor(y/dy) <= cy, a contiguous range; weight By_{cy - floor(y/dy)}.
@@ -327,6 +327,19 @@ __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, floa
     sm.YR[2 * cyl] = max(max(0, (cy - 3) * g.dy), b.y0) - b.y0;
     sm.YR[2 * cyl + 1] = max(min((cy + 1) * g.dy, b.ye) - b.y0, sm.YR[2 * cyl]);
   }
+}
+
+// Pass 1 for one brick.  Collective over the workgroup (kAdjThreads threads).
+template <int DX>
+__device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, float* __restrict__ part,
+                                          const AdjGeom& a, const float* __restrict__ lut, int brick,
+                                          AdjSmem<DX>& sm, int tid) {
+  const VolGeom& g = a.g;
+  const int dx = DX > 0 ? DX : g.dx;
+  const AdjBrick b = adj_brick_geom(a, brick);
+  float* pbase = part + (size_t)brick * a.z.cm * a.y.cm * a.x.cm * 3;
+
+  adj_tables(a, b, lut, sm.e, tid);
   // (the first y-contraction's barrier orders these writes before any read)
 
   const int txl = tid % kAdjTilesX;
@@ -368,7 +381,7 @@ __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, floa
       accw[n].z = fmaf(w, cw.z, accw[n].z);
     }
     if (++oz == g.dz && z + 1 < b.ze) {
-      adj_emit<DX>(a, b, pbase, sm, tid, tz - b.cz0, tz - b.cz0, false, acc[0], accw[0]);
+      adj_emit(a, b, pbase, sm.e, tid, tz - b.cz0, tz - b.cz0, false, acc[0], accw[0]);
 #pragma unroll
       for (int n = 0; n < 3; ++n) {
         acc[n] = acc[n + 1];
@@ -406,7 +419,7 @@ __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, floa
   // shifted through acc[0] so the emission is instantiated once more, not four times.
 #pragma unroll 1
   for (int n = 0; n < 4; ++n) {
-    adj_emit<DX>(a, b, pbase, sm, tid, tz - b.cz0 + n, tz - b.cz0 + n, n == 3, acc[0], accw[0]);
+    adj_emit(a, b, pbase, sm.e, tid, tz - b.cz0 + n, tz - b.cz0 + n, n == 3, acc[0], accw[0]);
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       acc[j] = acc[j + 1];

@@ -50,6 +50,12 @@ size_t ssd_partial_count(const VolGeom& g);
 hipError_t launch_ssd_grad(const float* field, const float* moving, const float* fixed,
                            const VolGeom& g, float* dfield, float* loss, float* partials,
                            hipStream_t s);
+// Fixed-order sum of n floats into out[0] (one workgroup).
+hipError_t launch_sum(const float* partials, long n, float* out, hipStream_t s);
+// Fused BSI -> warp -> SSD -> adjoint (fused.hip).
+size_t fused_workspace_bytes(const AdjGeom& a);
+hipError_t launch_ssd_fused(const float* grid, const float* moving, const float* fixed, float* grad, float* loss,
+                            const AdjGeom& a, const float* lut, void* workspace, hipStream_t s);
 hipError_t launch_descent(float* grid, const float* grad, float eta, int64_t count, hipStream_t s);
 
 }  // namespace bsi

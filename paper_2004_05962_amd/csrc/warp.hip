@@ -6,64 +6,13 @@
 // cell [p, p+1] is used; a coordinate on or beyond the border (p <= 0 or
 // p >= n-1) gets zero gradient.
 #include "bsi_internal.h"
+#include "warp_device.h"
 
 namespace bsi {
 
 namespace {
 
 constexpr int kRowThreads = 256;
-
-struct Axis {
-  int i0, i1;
-  float f;
-  float in;  // 1 where p is strictly inside (0, n-1), else 0
-};
-
-__device__ __forceinline__ Axis make_axis(float p, int n) {
-  Axis a;
-  const float top = (float)(n - 1);
-  a.in = (p > 0.f && p < top) ? 1.f : 0.f;
-  const float pc = fminf(fmaxf(p, 0.f), top);  // NaN -> 0
-  int i = (int)floorf(pc);
-  i = min(i, n >= 2 ? n - 2 : 0);
-  a.i0 = i;
-  a.i1 = min(i + 1, n - 1);
-  a.f = n >= 2 ? pc - (float)i : 0.f;
-  return a;
-}
-
-struct Sample {
-  float w;            // interpolated value
-  float gx, gy, gz;   // dW/dp, masked at the border
-};
-
-__device__ __forceinline__ Sample trilinear(const float* __restrict__ img, int nx, int ny, int nz,
-                                            float px, float py, float pz) {
-  const Axis ax = make_axis(px, nx), ay = make_axis(py, ny), az = make_axis(pz, nz);
-  const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
-  const float* p00 = img + az.i0 * sz + ay.i0 * sy;
-  const float* p01 = img + az.i0 * sz + ay.i1 * sy;
-  const float* p10 = img + az.i1 * sz + ay.i0 * sy;
-  const float* p11 = img + az.i1 * sz + ay.i1 * sy;
-  const float c000 = p00[ax.i0], c001 = p00[ax.i1];
-  const float c010 = p01[ax.i0], c011 = p01[ax.i1];
-  const float c100 = p10[ax.i0], c101 = p10[ax.i1];
-  const float c110 = p11[ax.i0], c111 = p11[ax.i1];
-  const float fx = ax.f, fy = ay.f, fz = az.f;
-  // interpolate along x, then y, then z
-  const float x00 = fmaf(fx, c001 - c000, c000), x01 = fmaf(fx, c011 - c010, c010);
-  const float x10 = fmaf(fx, c101 - c100, c100), x11 = fmaf(fx, c111 - c110, c110);
-  const float y0 = fmaf(fy, x01 - x00, x00), y1 = fmaf(fy, x11 - x10, x10);
-  Sample s;
-  s.w = fmaf(fz, y1 - y0, y0);
-  // analytic derivatives of the trilinear form
-  const float dx00 = c001 - c000, dx01 = c011 - c010, dx10 = c101 - c100, dx11 = c111 - c110;
-  const float dx0 = fmaf(fy, dx01 - dx00, dx00), dx1 = fmaf(fy, dx11 - dx10, dx10);
-  s.gx = fmaf(fz, dx1 - dx0, dx0) * ax.in;
-  s.gy = fmaf(fz, (x11 - x10) - (x01 - x00), x01 - x00) * ay.in;
-  s.gz = (y1 - y0) * az.in;
-  return s;
-}
 
 __global__ __launch_bounds__(kRowThreads) void warp_kernel(const float* __restrict__ field,
                                                             const float* __restrict__ image, VolGeom g,
@@ -156,7 +105,11 @@ hipError_t launch_ssd_grad(const float* field, const float* moving, const float*
                      dfield, partials, nbx);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(kReduceThreads), 0, s, partials, blocks, loss);
+  return launch_sum(partials, blocks, loss, s);
+}
+
+hipError_t launch_sum(const float* partials, long n, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(kReduceThreads), 0, s, partials, n, out);
   return hipGetLastError();
 }
 

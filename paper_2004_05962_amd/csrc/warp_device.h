@@ -1,0 +1,66 @@
+// Trilinear sampling of a scalar image at p = x + T(x) with its analytic
+// gradient: the image side of the SSD registration step.
+//
+// p is formed in FP32 (the precision that decides the cell); corners on voxel
+// centres, p clamped to [0, n-1]; at an exact integer p the cell [p, p+1] is
+// used; a coordinate on or beyond the border (p <= 0 or p >= n-1) gets zero
+// gradient.
+#pragma once
+
+#include "bsi_device.h"
+
+namespace bsi {
+
+struct Axis {
+  int i0, i1;
+  float f;
+  float in;  // 1 where p is strictly inside (0, n-1), else 0
+};
+
+__device__ __forceinline__ Axis sample_axis(float p, int n) {
+  Axis a;
+  const float top = (float)(n - 1);
+  a.in = (p > 0.f && p < top) ? 1.f : 0.f;
+  const float pc = fminf(fmaxf(p, 0.f), top);  // NaN -> 0
+  int i = (int)floorf(pc);
+  i = min(i, n >= 2 ? n - 2 : 0);
+  a.i0 = i;
+  a.i1 = min(i + 1, n - 1);
+  a.f = n >= 2 ? pc - (float)i : 0.f;
+  return a;
+}
+
+struct Sample {
+  float w;            // interpolated value
+  float gx, gy, gz;   // dW/dp, masked at the border
+};
+
+__device__ __forceinline__ Sample trilinear(const float* __restrict__ img, int nx, int ny, int nz,
+                                            float px, float py, float pz) {
+  const Axis ax = sample_axis(px, nx), ay = sample_axis(py, ny), az = sample_axis(pz, nz);
+  const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+  const float* p00 = img + az.i0 * sz + ay.i0 * sy;
+  const float* p01 = img + az.i0 * sz + ay.i1 * sy;
+  const float* p10 = img + az.i1 * sz + ay.i0 * sy;
+  const float* p11 = img + az.i1 * sz + ay.i1 * sy;
+  const float c000 = p00[ax.i0], c001 = p00[ax.i1];
+  const float c010 = p01[ax.i0], c011 = p01[ax.i1];
+  const float c100 = p10[ax.i0], c101 = p10[ax.i1];
+  const float c110 = p11[ax.i0], c111 = p11[ax.i1];
+  const float fx = ax.f, fy = ay.f, fz = az.f;
+  // interpolate along x, then y, then z
+  const float x00 = fmaf(fx, c001 - c000, c000), x01 = fmaf(fx, c011 - c010, c010);
+  const float x10 = fmaf(fx, c101 - c100, c100), x11 = fmaf(fx, c111 - c110, c110);
+  const float y0 = fmaf(fy, x01 - x00, x00), y1 = fmaf(fy, x11 - x10, x10);
+  Sample s;
+  s.w = fmaf(fz, y1 - y0, y0);
+  // analytic derivatives of the trilinear form
+  const float dx00 = c001 - c000, dx01 = c011 - c010, dx10 = c101 - c100, dx11 = c111 - c110;
+  const float dx0 = fmaf(fy, dx01 - dx00, dx00), dx1 = fmaf(fy, dx11 - dx10, dx10);
+  s.gx = fmaf(fz, dx1 - dx0, dx0) * ax.in;
+  s.gy = fmaf(fz, (x11 - x10) - (x01 - x00), x01 - x00) * ay.in;
+  s.gz = (y1 - y0) * az.in;
+  return s;
+}
+
+}  // namespace bsi

@@ -6,18 +6,21 @@ similarity standing in for the paper's NiftyReg measure):
   loss, dL/dfield                       bsi_ssd_grad
   g = B^T dL/dfield                     bsi_adjoint
   grid -= eta * g                       bsi_descent_step
-All four run on one stream; losses are written into a device buffer, so the host
+With ``fused=True`` (the default) the first three are one call, bsi_ssd_fused,
+which never stores the field or dL/dfield (the merge of FFD steps into BSI that
+Sec. 8 names as further work); the results agree up to FP32 rounding.
+All calls run on one stream; losses are written into a device buffer, so the host
 synchronises only when it reads them.  ``losses[s]`` is the loss of grid_s,
 before its update.  State for checkpoint/resume is (grid, step, eta).
 """
 import torch
 
-from ._lib import (bsi_adjoint, bsi_adjoint_workspace_size, bsi_descent_step, bsi_forward,
-                   bsi_ssd_grad, bsi_ssd_workspace_size, field_shape, grid_shape)
+from ._lib import (bsi_adjoint, bsi_adjoint_workspace_size, bsi_descent_step, bsi_forward, bsi_ssd_fused,
+                   bsi_ssd_fused_workspace_size, bsi_ssd_grad, bsi_ssd_workspace_size, field_shape, grid_shape)
 
 
 class SSDRegistration:
-    def __init__(self, fixed, moving, spacing, grid=None, eta=None, max_steps=1024):
+    def __init__(self, fixed, moving, spacing, grid=None, eta=None, max_steps=1024, fused=True):
         if fixed.shape != moving.shape or fixed.dim() != 3:
             raise ValueError("fixed and moving must be (nz, ny, nx) images of one shape")
         nz, ny, nx = fixed.shape
@@ -29,11 +32,17 @@ class SSDRegistration:
         gshape = grid_shape(self.dims, self.spacing)
         self.grid = (torch.zeros(gshape, dtype=torch.float32, device=dev) if grid is None
                      else grid.to(device=dev, dtype=torch.float32).contiguous().clone())
-        self.field = torch.empty(field_shape(self.dims), dtype=torch.float32, device=dev)
-        self.dfield = torch.empty_like(self.field)
+        self.fused = bool(fused)
         self.grad = torch.empty(gshape, dtype=torch.float32, device=dev)
-        self.ws_adj = torch.empty(bsi_adjoint_workspace_size(self.dims, self.spacing), dtype=torch.uint8, device=dev)
-        self.ws_ssd = torch.empty(bsi_ssd_workspace_size(self.dims), dtype=torch.uint8, device=dev)
+        if self.fused:
+            self.ws_fused = torch.empty(bsi_ssd_fused_workspace_size(self.dims, self.spacing), dtype=torch.uint8,
+                                        device=dev)
+        else:
+            self.field = torch.empty(field_shape(self.dims), dtype=torch.float32, device=dev)
+            self.dfield = torch.empty_like(self.field)
+            self.ws_adj = torch.empty(bsi_adjoint_workspace_size(self.dims, self.spacing), dtype=torch.uint8,
+                                      device=dev)
+            self.ws_ssd = torch.empty(bsi_ssd_workspace_size(self.dims), dtype=torch.uint8, device=dev)
         self.losses = torch.zeros(max_steps, dtype=torch.float32, device=dev)
         self.step_index = 0
         self.eta = eta
@@ -41,6 +50,10 @@ class SSDRegistration:
     def evaluate(self, loss_out=None, stream=None):
         """Loss and gradient at the current grid (no update); gradient in self.grad."""
         loss_out = self.losses[self.step_index:self.step_index + 1] if loss_out is None else loss_out
+        if self.fused:
+            bsi_ssd_fused(self.grid, self.moving, self.fixed, self.dims, self.spacing, self.grad, loss_out,
+                          self.ws_fused, stream)
+            return loss_out
         bsi_forward(self.grid, self.dims, self.spacing, self.field, stream)
         bsi_ssd_grad(self.field, self.moving, self.fixed, self.dims, self.dfield, loss_out, self.ws_ssd, stream)
         bsi_adjoint(self.dfield, self.dims, self.spacing, self.grad, self.ws_adj, stream)

@@ -86,6 +86,10 @@ def test_null_pointers_rejected_before_device():
     assert _call("bsi_adjoint_reduce", NULL, 1 << 30, d, s, P, NULL) == _lib.BSI_ERR_INVALID_ARG
     assert _call("bsi_warp", NULL, P, d, P, NULL) == _lib.BSI_ERR_INVALID_ARG
     assert _call("bsi_ssd_grad", P, P, P, d, P, NULL, P, 1 << 30, NULL) == _lib.BSI_ERR_INVALID_ARG
+    for k in range(6):
+        args = [P, P, P, d, s, P, P, P, 1 << 30, NULL]
+        args[[0, 1, 2, 5, 6, 7][k]] = NULL
+        assert _call("bsi_ssd_fused", *args) == _lib.BSI_ERR_INVALID_ARG
     assert _call("bsi_descent_step", NULL, P, ctypes.c_float(1.0), 4, NULL) == _lib.BSI_ERR_INVALID_ARG
     assert _call("bsi_descent_step", P, P, ctypes.c_float(1.0), -1, NULL) == _lib.BSI_ERR_INVALID_ARG
     assert "non-null" in bsi.bsi_last_error() or "count" in bsi.bsi_last_error()
@@ -99,6 +103,9 @@ def test_workspace_size_checked_before_device():
     assert "workspace too small" in bsi.bsi_last_error()
     assert _call("bsi_adjoint_partials", P, d, s, P, need - 1, NULL) == _lib.BSI_ERR_INVALID_ARG
     assert _call("bsi_adjoint_reduce", P, need - 1, d, s, P, NULL) == _lib.BSI_ERR_INVALID_ARG
+    fused = bsi.bsi_ssd_fused_workspace_size((40, 30, 20), (5, 5, 5))
+    assert fused > need
+    assert _call("bsi_ssd_fused", P, P, P, d, s, P, P, P, fused - 1, NULL) == _lib.BSI_ERR_INVALID_ARG
     ssd = bsi.bsi_ssd_workspace_size((40, 30, 20))
     assert _call("bsi_ssd_grad", P, P, P, d, P, P, P, ssd - 1, NULL) == _lib.BSI_ERR_INVALID_ARG
 

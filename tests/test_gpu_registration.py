@@ -60,12 +60,13 @@ def test_descent_step():
     assert (g.double() - expect).abs().max().item() <= 1e-6
 
 
-def test_registration_trajectory_matches_oracle():
+@pytest.mark.parametrize("fused", [True, False])
+def test_registration_trajectory_matches_oracle(fused):
     dims = (48, 40, 32)
     case, moving = _pair(dims, nblobs=20)
     fixed, spacing = case["fixed"], case["spacing"]
-    say("registration trajectory", dims)
-    reg = bsi.SSDRegistration(dev(fixed), dev(moving), spacing)
+    say("registration trajectory", dims, "fused" if fused else "unfused")
+    reg = bsi.SSDRegistration(dev(fixed), dev(moving), spacing, fused=fused)
     eta = 0.5 / float(np.abs(oreg.step(np.zeros(case["grid_true"].shape), moving, fixed, spacing)[1]).max())
     reg.eta = eta
     losses = host(reg.run(50))
