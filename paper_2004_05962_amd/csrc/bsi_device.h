@@ -72,6 +72,16 @@ __device__ __forceinline__ int xcd_remap(int id, int n) {
 __device__ __forceinline__ F3 ldf3(const float* p) { return *reinterpret_cast<const F3*>(p); }
 __device__ __forceinline__ void stf3(float* p, F3 v) { *reinterpret_cast<F3*>(p) = v; }
 
+// Streaming store of the dense field: non-temporal, so the write stream does not
+// evict the control points that neighbouring waves still read from L2.
+// (12-byte stores straight from the lanes measured faster than staging the
+// wave's row through LDS into 16-byte stores.)
+__device__ __forceinline__ void stf3_stream(float* p, F3 v) {
+  __builtin_nontemporal_store(v.x, p);
+  __builtin_nontemporal_store(v.y, p + 1);
+  __builtin_nontemporal_store(v.z, p + 2);
+}
+
 // ----------------------------------------------------------------------------
 // Forward BSI for one workgroup: kFwdRows consecutive rows y0.. of the 64-voxel
 // x-strip x0..x0+63 (lane = x), voxel planes z0..z1-1.  All bounds are
@@ -87,9 +97,8 @@ __device__ __forceinline__ void stf3(float* p, F3 v) { *reinterpret_cast<F3*>(p)
 // (a window of at most kFwdMaxCy x kFwdMaxCx points) are staged once in a
 // two-slot LDS ring: the next plane is loaded into registers (a few floats per
 // thread, coalesced rows) while the current tile is written, then stored to the
-// free slot; one barrier per tile.  A wave's 64 voxels of a plane (768
-// contiguous bytes) go out through a small wave-private LDS row as 16-byte
-// stores (fwd_store_row).
+// free slot; one barrier per tile.  Each voxel is one 12-byte store, so a wave
+// writes 768 contiguous bytes per plane.
 // ----------------------------------------------------------------------------
 #ifndef BSI_FWD_ROWS
 #define BSI_FWD_ROWS 4
@@ -102,13 +111,8 @@ constexpr int kFwdPitch = kFwdMaxCx * 3;               // floats per staged cont
 constexpr int kFwdPlane = kFwdMaxCy * kFwdPitch;       // floats per staged plane
 constexpr int kFwdLoads = (kFwdPlane + kFwdThreads - 1) / kFwdThreads;
 
-// Output row of one wave: 64 voxels x 3 floats, shifted by up to 3 floats so
-// that LDS float4 j maps onto a 16-byte-aligned float4 of the field.
-constexpr int kFwdOutRow = kWave * 3 + 4;
-
 struct FwdSmem {
   float ring[2][kFwdLoads * kFwdThreads];
-  float out[2][kFwdRows][kFwdOutRow];  // double-buffered per wave
 };
 
 // Staging map: thread tid moves floats e = tid + k * kFwdThreads of the window,
@@ -169,40 +173,6 @@ __device__ __forceinline__ F3 fwd_contract(const float* __restrict__ slot, int b
   return q;
 }
 
-// Store one wave's row segment of a voxel plane: lane j holds voxel x0 + j
-// (valid for j < nv) that belongs at row[3j .. 3j+2].  The values pass through
-// the wave's LDS row `buf`, written at float offset ph + 3j where ph is the
-// row's position inside its 16-byte block, so that LDS float4 j is exactly the
-// aligned field float4 at row - ph + 4j.  Lane j then stores that float4 with
-// one 16-byte non-temporal store when it lies inside the segment, or its
-// floats one by one when it straddles an end (at most the first and last).
-// Every field address written is inside [row, row + 3 nv).  Collective over
-// the wave; buf must not be read by any lane of this wave until the next
-// wave_lds_sync (the caller alternates two buffers).
-typedef float fwd_f4 __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ void fwd_store_row(float* __restrict__ row, float* __restrict__ buf, int nv,
-                                              int lane, F3 t) {
-  const int ph = (int)((reinterpret_cast<uintptr_t>(row) >> 2) & 3);
-  float* e = buf + ph + 3 * lane;
-  e[0] = t.x;
-  e[1] = t.y;
-  e[2] = t.z;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-  const int lo = 4 * lane, end = ph + 3 * nv;
-  if (lo >= end) return;
-  const fwd_f4 v = *reinterpret_cast<const fwd_f4*>(buf + lo);
-  float* dst = row - ph + lo;
-  if (lo >= ph && lo + 4 <= end) {
-    __builtin_nontemporal_store(v, reinterpret_cast<fwd_f4*>(dst));
-  } else {
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-      if (lo + i >= ph && lo + i < end) __builtin_nontemporal_store(v[i], dst + i);
-  }
-}
-
 // Collective over the workgroup (kFwdThreads threads, all bounds uniform).
 __device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float* __restrict__ field,
                                           const VolGeom& g, const float* __restrict__ lut, int x0, int y0,
@@ -217,8 +187,7 @@ __device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float*
 
   const int x = x0 + lane;
   const int y = y0 + wave;
-  const bool wave_active = y < g.ny;  // wave-uniform
-  const int nv = min(kWave, g.nx - x0);
+  const bool active = x < g.nx && y < g.ny;
   const int xc = min(x, g.nx - 1);  // idle lanes read a valid column, store nothing
   const int yc = min(y, g.ny - 1);
   const int tx = xc / g.dx;
@@ -255,8 +224,7 @@ __device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float*
   int slot3 = 1;  // slot holding plane tz + 3
 
   const size_t zstride = (size_t)g.ny * g.nx * 3;
-  float* out = field + (((size_t)z0 * g.ny + yc) * g.nx + x0) * 3;  // row segment start
-  int ob = 0;  // output buffer of this plane
+  float* out = field + (((size_t)z0 * g.ny + yc) * g.nx + xc) * 3;
   int z = z0;
   for (;;) {
     const F3 q3 = fwd_contract(sm.ring[slot3], base, bx0, bx1, bx2, bx3, wy);
@@ -272,8 +240,7 @@ __device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float*
       t.x = fmaf(w3, q3.x, fmaf(w2, q2.x, fmaf(w1, q1.x, w0 * q0.x)));
       t.y = fmaf(w3, q3.y, fmaf(w2, q2.y, fmaf(w1, q1.y, w0 * q0.y)));
       t.z = fmaf(w3, q3.z, fmaf(w2, q2.z, fmaf(w1, q1.z, w0 * q0.z)));
-      if (wave_active) fwd_store_row(out, sm.out[ob][wave], nv, lane, t);
-      ob ^= 1;
+      if (active) stf3_stream(out, t);
       out += zstride;
     }
     if (!more) break;
