@@ -96,23 +96,49 @@ def time_events(torch, fn, reps, flush=None):
     return out
 
 
-def cpu_baseline(grid_np, dfield_np, dims, spacing, planes=128):
-    """FP64 oracle, forward + adjoint, on the first `planes` z-planes."""
+def cpu_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+def cpu_baseline(grid_np, dfield_np, dims, spacing, planes=128, planes_1t=16):
+    """FP64 oracle, forward + adjoint, on the first `planes` z-planes with all
+    the host's threads, and its forward on the first `planes_1t` planes with one."""
     import oracle
     d = spacing[2]
-    sub_dims = (dims[0], dims[1], planes)
-    gz = -(-planes // d) + 3
-    g = grid_np[:gz]
-    y = dfield_np[:planes]
+
+    def sub(p):
+        return (dims[0], dims[1], p), grid_np[:-(-p // d) + 3], dfield_np[:p]
+
+    sub_dims, g, y = sub(planes)
     t0 = time.perf_counter()
     oracle.forward(g, sub_dims, spacing)
     t1 = time.perf_counter()
     oracle.adjoint(y, sub_dims, spacing)
     t2 = time.perf_counter()
+    threads = oracle.num_threads()
+    dims1, g1, _ = sub(planes_1t)
+    oracle.set_num_threads(1)
+    t3 = time.perf_counter()
+    oracle.forward(g1, dims1, spacing)
+    t4 = time.perf_counter()
+    oracle.set_num_threads(threads)
     vox = dims[0] * dims[1] * planes
-    return {"value": vox / (t2 - t0) / 1e9, "unit": "GVoxel/s", "cores": oracle.num_threads(), "kind": "oracle",
+    vox1 = dims[0] * dims[1] * planes_1t
+    model, affinity = cpu_info()
+    return {"value": vox / (t2 - t0) / 1e9, "unit": "GVoxel/s", "cores": threads, "kind": "oracle",
             "sample": f"first {planes} of {dims[2]} z-planes ({vox / 1e6:.1f} M voxels), forward {t1 - t0:.2f} s "
-                      f"(OpenMP) + adjoint {t2 - t1:.2f} s (serial scatter), FP64"}
+                      f"(OpenMP) + adjoint {t2 - t1:.2f} s (serial scatter), FP64",
+            "forward_gvoxel_s": vox / (t1 - t0) / 1e9, "adjoint_gvoxel_s": vox / (t2 - t1) / 1e9,
+            "forward_1_thread_gvoxel_s": vox1 / (t4 - t3) / 1e9, "cpu_model": model, "affinity_cpus": affinity}
 
 
 def main():
@@ -203,6 +229,22 @@ def main():
              "adjoint_gvoxel_s": round(V / (adj_ms * 1e-3) / 1e9, 2)}
     log("main:", json.dumps(other))
 
+    # ceilings measured live on this GPU with plain torch kernels of the same size:
+    # a fill (write-only) and a copy, each on 805,306,368 bytes
+    nb = 12 * V
+    a_buf = torch.empty(nb // 4, device="cuda")
+    b_buf = torch.empty_like(a_buf)
+    a_buf.fill_(1.0)
+    fill_gbs = nb / median(time_events(torch, lambda: a_buf.fill_(2.0), 10)) / 1e6
+    copy_gbs = 2 * nb / median(time_events(torch, lambda: b_buf.copy_(a_buf), 10)) / 1e6
+    del a_buf, b_buf
+    fwd_gbs = fwd_bytes / (fwd_ms * 1e-3) / 1e9
+    p1_gbs = p1_bytes / (p1_ms * 1e-3) / 1e9
+    ceilings = {"fill_gbs": round(fill_gbs, 1), "copy_gbs": round(copy_gbs, 1),
+                "forward_frac_of_fill": round(fwd_gbs / fill_gbs, 4),
+                "adjoint_pass1_frac_of_copy": round(p1_gbs / copy_gbs, 4)}
+    log("ceilings:", json.dumps(ceilings))
+
     if args.copy_calibration:
         src = torch.ones(805306368 // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -225,7 +267,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "BSI forward + adjoint, 512x512x256 voxels, spacing 5, grid 106x106x55x3",
                    "global_batch": 1, "voxels": V, "spacing": list(spacing), "parallelism": "single GPU"},
-        "roofline": roofline, "cpu_baseline": cpu, "breakdown": other, "extras": extras,
+        "roofline": roofline, "cpu_baseline": cpu, "breakdown": other, "ceilings": ceilings, "extras": extras,
     }
     print(json.dumps(out), flush=True)
 

@@ -43,6 +43,8 @@ def _lib():
         lib.oracle_basis.restype = None
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_num_threads.restype = None
         for name in ("oracle_forward", "oracle_forward_lerp"):
             getattr(lib, name).argtypes = [f64p, i32p, i32p, f64p]
             getattr(lib, name).restype = ctypes.c_int
@@ -58,6 +60,11 @@ def _lib():
 def num_threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(_lib().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads for the oracle's later OpenMP loops."""
+    _lib().oracle_set_num_threads(int(n))
 
 
 def grid_dims(dims, spacing):

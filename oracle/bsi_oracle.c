@@ -46,6 +46,16 @@ int oracle_num_threads(void) {
 #endif
 }
 
+/* Threads for the OpenMP loops that follow (n >= 1); used to time the oracle
+   on one core as well as on all of them. */
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Uniform cubic B-spline basis at local coordinate u in [0,1) (Eq. 1's B_l). */
 void oracle_basis(double u, double B[4]) {
     double v = 1.0 - u;

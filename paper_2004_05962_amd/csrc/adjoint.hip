@@ -85,6 +85,7 @@ hipError_t launch_adjoint_partials(const float* dfield, const AdjGeom& a, const 
                                   hipStream_t s) {
   const long nbricks = (long)a.x.nb * a.y.nb * a.z.nb;
   const dim3 grid((unsigned)nbricks), block(kAdjThreads);
+  static_assert(kAdjMaxDX == 12, "one case per specialised spacing");
   switch (a.g.dx) {
     case 1: hipLaunchKernelGGL(adj_pass1_kernel<1>, grid, block, 0, s, dfield, part, a, lut); break;
     case 2: hipLaunchKernelGGL(adj_pass1_kernel<2>, grid, block, 0, s, dfield, part, a, lut); break;
@@ -94,6 +95,10 @@ hipError_t launch_adjoint_partials(const float* dfield, const AdjGeom& a, const 
     case 6: hipLaunchKernelGGL(adj_pass1_kernel<6>, grid, block, 0, s, dfield, part, a, lut); break;
     case 7: hipLaunchKernelGGL(adj_pass1_kernel<7>, grid, block, 0, s, dfield, part, a, lut); break;
     case 8: hipLaunchKernelGGL(adj_pass1_kernel<8>, grid, block, 0, s, dfield, part, a, lut); break;
+    case 9: hipLaunchKernelGGL(adj_pass1_kernel<9>, grid, block, 0, s, dfield, part, a, lut); break;
+    case 10: hipLaunchKernelGGL(adj_pass1_kernel<10>, grid, block, 0, s, dfield, part, a, lut); break;
+    case 11: hipLaunchKernelGGL(adj_pass1_kernel<11>, grid, block, 0, s, dfield, part, a, lut); break;
+    case 12: hipLaunchKernelGGL(adj_pass1_kernel<12>, grid, block, 0, s, dfield, part, a, lut); break;
     default: hipLaunchKernelGGL(adj_pass1_kernel<0>, grid, block, 0, s, dfield, part, a, lut); break;
   }
   return hipGetLastError();

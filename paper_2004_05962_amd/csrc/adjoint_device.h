@@ -53,7 +53,7 @@ constexpr int kAdjSlots = 512;
 #define BSI_ADJ_TARGET_Z 24
 #endif
 constexpr int kAdjTargetZ = BSI_ADJ_TARGET_Z;       // brick depth bound (voxels)
-constexpr int kAdjMaxDX = 8;                        // largest specialised x spacing
+constexpr int kAdjMaxDX = 12;                       // largest specialised x spacing
 constexpr int kAdjChunk = 4;                        // generic path: voxels per step
 static_assert(kWave % kAdjTilesX == 0, "a wave holds whole rows of tiles");
 

@@ -214,6 +214,7 @@ hipError_t launch_pass(bsi_batch* p, int pass, hipStream_t s) {
       const int64_t cg = per_cu == 0 ? ct : std::min<int64_t>(ct, (int64_t)per_cu * p->cus);
       const dim3 gd((unsigned)cg), bd(kAdjThreads);
       const VolDesc* v = p->d_cls + p->cls_first[c];
+      static_assert(kAdjMaxDX == 12, "one case per specialised spacing");
       switch (c) {
         case 1: hipLaunchKernelGGL(batch_adj1_kernel<1>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
         case 2: hipLaunchKernelGGL(batch_adj1_kernel<2>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
@@ -223,6 +224,10 @@ hipError_t launch_pass(bsi_batch* p, int pass, hipStream_t s) {
         case 6: hipLaunchKernelGGL(batch_adj1_kernel<6>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
         case 7: hipLaunchKernelGGL(batch_adj1_kernel<7>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
         case 8: hipLaunchKernelGGL(batch_adj1_kernel<8>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+        case 9: hipLaunchKernelGGL(batch_adj1_kernel<9>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+        case 10: hipLaunchKernelGGL(batch_adj1_kernel<10>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+        case 11: hipLaunchKernelGGL(batch_adj1_kernel<11>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+        case 12: hipLaunchKernelGGL(batch_adj1_kernel<12>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
         default: hipLaunchKernelGGL(batch_adj1_kernel<0>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
       }
       hipError_t e = hipGetLastError();

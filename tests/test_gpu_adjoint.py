@@ -26,6 +26,11 @@ CASES = [
     ((33, 40, 129), (8, 33, 6)),      # y spacing above the 32-row brick: unaligned bricks
     ((96, 80, 72), (3, 5, 8)),
     ((61, 47, 53), (2, 2, 2)),
+    ((100, 30, 20), (9, 4, 3)),       # the larger specialised x spacings, ragged
+    ((130, 40, 17), (10, 5, 6)),
+    ((77, 35, 29), (11, 3, 7)),
+    ((200, 33, 9), (12, 12, 2)),
+    ((91, 20, 12), (13, 2, 3)),       # first spacing on the generic x path
 ]
 
 
