@@ -15,10 +15,16 @@
 //             column c (and column c + 16 for lanes < 3), control planes
 //             tz..tz+3 kept in a rolling window, one new plane per z-tile;
 //   P(c)    = sum_n Bz_n(w) R_n(c)               once per voxel plane;
-//   T(o)    = sum_l Bx_l(o) P(tx + l)            per voxel, the three
-//             neighbouring columns taken from the row's other lanes (DPP).
-// The voxel's gradient 2 (W - fixed) dW/dp then enters the x-moments exactly
-// where the adjoint's dfield value would, and the rest is the adjoint's pass 1.
+//   T(o)    = sum_l Bx_l(o) P(tx + l)            per voxel.
+// For spacings up to kFusedMaxDX the per-voxel work runs in voxel layout: each
+// wave publishes its rows' P in LDS, every lane takes voxels k * 64 + lane of
+// the wave's 4 rows (consecutive lanes on consecutive voxels, so the image
+// loads coalesce), evaluates T, samples the moving image and writes the
+// voxel's gradient 2 (W - fixed) dW/dp into the wave's transpose buffer, from
+// which the tile lanes read their rows: from there on it is the adjoint's
+// pass 1 with this gradient in place of dfield.  Larger spacings do the same
+// per tile lane, the three neighbouring columns of P taken from the row's
+// other lanes (DPP).
 // Each workgroup also sums its voxels' squared residuals in a fixed order into
 // one loss partial; pass 2 is the adjoint's fixed-order gather, and the loss is
 // the fixed-order sum of the partials.  No atomics: the bits depend on the
@@ -31,9 +37,22 @@ namespace bsi {
 
 namespace {
 
+// Spacings that take the warp in voxel layout (below); larger ones evaluate it
+// in tile layout.
+constexpr int kFusedMaxDX = 8;
+constexpr int kFusedCols = kAdjTilesX + 3;  // window columns of one brick row
+
+__host__ __device__ constexpr bool fused_voxel_layout(int dx) { return dx >= 1 && dx <= kFusedMaxDX; }
+
+template <int DX>
 struct FusedSmem {
   AdjEmitSmem e;
   float red[kAdjThreads];
+  // per wave: column values P of its 4 rows, and the transpose buffer that
+  // carries each voxel's gradient from voxel lanes to tile lanes
+  float P[fused_voxel_layout(DX) ? kAdjWaves * kAdjRowsPerWave * kFusedCols * 3 : 1];
+  float T[fused_voxel_layout(DX) ? kAdjWaves * adj_wave_buf(DX) : 1];
+  float wx[fused_voxel_layout(DX) ? 4 * DX : 1];  // x weights of the offsets 0..DX-1
 };
 
 // Value of lane (i + L) mod 16 of this lane's row of 16 lanes.
@@ -60,11 +79,15 @@ template <int DX>
 __device__ __forceinline__ void fused_brick(const float* __restrict__ grid, const float* __restrict__ moving,
                                             const float* __restrict__ fixed, float* __restrict__ part,
                                             float* __restrict__ lpart, const AdjGeom& a,
-                                            const float* __restrict__ lut, int brick, FusedSmem& sm, int tid) {
+                                            const float* __restrict__ lut, int brick, FusedSmem<DX>& sm,
+                                            int tid) {
   const VolGeom& g = a.g;
   const int dx = DX > 0 ? DX : g.dx;
   const AdjBrick b = adj_brick_geom(a, brick);
   float* pbase = part + (size_t)brick * a.z.cm * a.y.cm * a.x.cm * 3;
+  if constexpr (fused_voxel_layout(DX)) {
+    if (tid < 4 * DX) sm.wx[tid] = lut_row(lut, DX, 0)[tid];  // ordered by adj_tables' barrier
+  }
   adj_tables(a, b, lut, sm.e, tid);
 
   const int txl = tid % kAdjTilesX;
@@ -118,41 +141,74 @@ __device__ __forceinline__ void fused_brick(const float* __restrict__ grid, cons
 
   for (int z = b.z0; z < b.ze; ++z) {
     const float* wz = lut_row(lut, g.dz, oz);
-    // P of the four columns tx..tx+3 of this plane (every lane takes part)
-    F3 P[4];
-    P[0] = zcombine(wz, R);
-    const F3 pw = zcombine(wz, Rw);
-    P[1] = column_right<1>(txl, P[0], pw);
-    P[2] = column_right<2>(txl, P[0], pw);
-    P[3] = column_right<3>(txl, P[0], pw);
-
     F3 M[4];
-#pragma unroll
-    for (int l = 0; l < 4; ++l) M[l] = F3{0.f, 0.f, 0.f};
-    auto voxel = [&](int o) {
-      const float* bx = lutx + 4 * o;
-      F3 t;
-      t.x = fmaf(bx[3], P[3].x, fmaf(bx[2], P[2].x, fmaf(bx[1], P[1].x, bx[0] * P[0].x)));
-      t.y = fmaf(bx[3], P[3].y, fmaf(bx[2], P[2].y, fmaf(bx[1], P[1].y, bx[0] * P[0].y)));
-      t.z = fmaf(bx[3], P[3].z, fmaf(bx[2], P[2].z, fmaf(bx[1], P[1].z, bx[0] * P[0].z)));
-      const Sample s = trilinear(moving, g.nx, g.ny, g.nz, (float)(x0 + o) + t.x, (float)y + t.y,
-                                 (float)z + t.z);
-      const float r = s.w - fix[o];
-      l2 = fmaf(r, r, l2);
-      const float two_r = 2.f * r;
-      const F3 d{two_r * s.gx, two_r * s.gy, two_r * s.gz};
-#pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        M[l].x = fmaf(bx[l], d.x, M[l].x);
-        M[l].y = fmaf(bx[l], d.y, M[l].y);
-        M[l].z = fmaf(bx[l], d.z, M[l].z);
+    const F3 pm = zcombine(wz, R);  // P of column tx (every lane takes part)
+    const F3 pw = zcombine(wz, Rw); // P of column tx + 16 (lanes txl < 3)
+    if constexpr (fused_voxel_layout(DX)) {
+      const int lane = tid & (kWave - 1), wave = tid / kWave;
+      float* pl = sm.P + wave * (kAdjRowsPerWave * kFusedCols * 3);
+      float* tb = sm.T + wave * adj_wave_buf(DX);
+      const int ywave = b.y0 + wave * kAdjRowsPerWave;
+      wave_lds_sync();  // the previous plane's readers of pl and tb are done
+      {
+        const int r = lane / kAdjTilesX;
+        stf3(pl + (r * kFusedCols + txl) * 3, pm);
+        if (txl < 3) stf3(pl + (r * kFusedCols + kAdjTilesX + txl) * 3, pw);
       }
-    };
-    if constexpr (DX > 0 && DX <= 5) {  // short rows unrolled; longer ones stay rolled (registers)
-#pragma unroll
-      for (int o = 0; o < DX; ++o)
-        if (o < nval) voxel(o);
+      wave_lds_sync();
+#pragma unroll 2
+      for (int k = 0; k < DX; ++k) {
+        const int v = k * kWave + lane;
+        const int r = v / (kAdjTilesX * DX);
+        const int xl = v - r * (kAdjTilesX * DX);
+        const int tl = xl / DX, o = xl - tl * DX;
+        const int xv = b.x0 + xl, yv = ywave + r;
+        F3 d{0.f, 0.f, 0.f};
+        if (xv < b.xe && yv < b.ye) {
+          const float* bx = sm.wx + 4 * o;
+          const float* pp = pl + (r * kFusedCols + tl) * 3;  // columns tl .. tl + 3 (<= 18)
+          F3 t;
+          t.x = fmaf(bx[3], pp[9], fmaf(bx[2], pp[6], fmaf(bx[1], pp[3], bx[0] * pp[0])));
+          t.y = fmaf(bx[3], pp[10], fmaf(bx[2], pp[7], fmaf(bx[1], pp[4], bx[0] * pp[1])));
+          t.z = fmaf(bx[3], pp[11], fmaf(bx[2], pp[8], fmaf(bx[1], pp[5], bx[0] * pp[2])));
+          const Sample smp = trilinear(moving, g.nx, g.ny, g.nz, (float)xv + t.x, (float)yv + t.y, (float)z + t.z);
+          const float res = smp.w - fixed[((size_t)z * g.ny + yv) * g.nx + xv];
+          l2 = fmaf(res, res, l2);
+          const float two_r = 2.f * res;
+          d = F3{two_r * smp.gx, two_r * smp.gy, two_r * smp.gz};
+        }
+        stf3(tb + v * 3, d);
+      }
+      wave_lds_sync();
+      adj_plane_moments<DX>(tb, lane, nval, lutx, M);
     } else {
+      // P of the four columns tx..tx+3 of this plane (every lane takes part)
+      F3 P[4];
+      P[0] = pm;
+      P[1] = column_right<1>(txl, pm, pw);
+      P[2] = column_right<2>(txl, pm, pw);
+      P[3] = column_right<3>(txl, pm, pw);
+#pragma unroll
+      for (int l = 0; l < 4; ++l) M[l] = F3{0.f, 0.f, 0.f};
+      auto voxel = [&](int o) {
+        const float* bx = lutx + 4 * o;
+        F3 t;
+        t.x = fmaf(bx[3], P[3].x, fmaf(bx[2], P[2].x, fmaf(bx[1], P[1].x, bx[0] * P[0].x)));
+        t.y = fmaf(bx[3], P[3].y, fmaf(bx[2], P[2].y, fmaf(bx[1], P[1].y, bx[0] * P[0].y)));
+        t.z = fmaf(bx[3], P[3].z, fmaf(bx[2], P[2].z, fmaf(bx[1], P[1].z, bx[0] * P[0].z)));
+        const Sample smp = trilinear(moving, g.nx, g.ny, g.nz, (float)(x0 + o) + t.x, (float)y + t.y,
+                                     (float)z + t.z);
+        const float res = smp.w - fix[o];
+        l2 = fmaf(res, res, l2);
+        const float two_r = 2.f * res;
+        const F3 d{two_r * smp.gx, two_r * smp.gy, two_r * smp.gz};
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+          M[l].x = fmaf(bx[l], d.x, M[l].x);
+          M[l].y = fmaf(bx[l], d.y, M[l].y);
+          M[l].z = fmaf(bx[l], d.z, M[l].z);
+        }
+      };
 #pragma unroll 1
       for (int o = 0; o < nval; ++o) voxel(o);
     }
@@ -215,7 +271,7 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(4))
                                                                    float* __restrict__ part,
                                                                    float* __restrict__ lpart, AdjGeom a,
                                                                    const float* __restrict__ lut) {
-  __shared__ FusedSmem sm;
+  __shared__ FusedSmem<DX> sm;
   const int nbricks = a.x.nb * a.y.nb * a.z.nb;
   const int brick = xcd_remap(blockIdx.x, gridDim.x);
   if (brick >= nbricks) return;  // uniform over the workgroup

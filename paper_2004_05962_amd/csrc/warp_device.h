@@ -30,6 +30,12 @@ __device__ __forceinline__ Axis sample_axis(float p, int n) {
   return a;
 }
 
+// Two consecutive floats, 4-byte aligned.
+struct __attribute__((packed, aligned(4))) F2 {
+  float x, y;
+};
+__device__ __forceinline__ F2 ldf2(const float* p) { return *reinterpret_cast<const F2*>(p); }
+
 struct Sample {
   float w;            // interpolated value
   float gx, gy, gz;   // dW/dp, masked at the border
@@ -43,10 +49,19 @@ __device__ __forceinline__ Sample trilinear(const float* __restrict__ img, int n
   const float* p01 = img + az.i0 * sz + ay.i1 * sy;
   const float* p10 = img + az.i1 * sz + ay.i0 * sy;
   const float* p11 = img + az.i1 * sz + ay.i1 * sy;
-  const float c000 = p00[ax.i0], c001 = p00[ax.i1];
-  const float c010 = p01[ax.i0], c011 = p01[ax.i1];
-  const float c100 = p10[ax.i0], c101 = p10[ax.i1];
-  const float c110 = p11[ax.i0], c111 = p11[ax.i1];
+  float c000, c001, c010, c011, c100, c101, c110, c111;
+  if (nx >= 2) {
+    // i1 = i0 + 1: each pair of x-neighbours is one 8-byte load
+    const F2 q00 = ldf2(p00 + ax.i0), q01 = ldf2(p01 + ax.i0);
+    const F2 q10 = ldf2(p10 + ax.i0), q11 = ldf2(p11 + ax.i0);
+    c000 = q00.x, c001 = q00.y, c010 = q01.x, c011 = q01.y;
+    c100 = q10.x, c101 = q10.y, c110 = q11.x, c111 = q11.y;
+  } else {
+    c000 = c001 = p00[0];
+    c010 = c011 = p01[0];
+    c100 = c101 = p10[0];
+    c110 = c111 = p11[0];
+  }
   const float fx = ax.f, fy = ay.f, fz = az.f;
   // interpolate along x, then y, then z
   const float x00 = fmaf(fx, c001 - c000, c000), x01 = fmaf(fx, c011 - c010, c010);
