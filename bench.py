@@ -18,7 +18,8 @@ Printed as ONE JSON line on stdout (logs go to stderr), with:
                 (MALL flushed between repetitions), the 32-volume batched
                 graph launch against per-volume launches, and one SSD
                 registration iteration at 256 x 256 x 160, fused (one pass,
-                no field in memory) and unfused (forward, SSD, adjoint).
+                no field in memory) and unfused (forward, SSD, adjoint), and
+                scalar B-spline upsampling to 512 x 512 x 256 (factor 4).
 """
 import argparse
 import hashlib
@@ -345,6 +346,21 @@ def run_extras(torch, bsi, workloads):
     log("batched:", ex["batched_32_volumes"])
     plan.close()
     del grids, dfields, fields, grads
+
+    # scalar B-spline upsampling: a 131 x 131 x 67 coarse volume (control points)
+    # to 512 x 512 x 256 voxels, factor 4 on every axis
+    dims_s, sp_s = (512, 512, 256), (4, 4, 4)
+    gx, gy, gz = bsi.bsi_grid_dims(dims_s, sp_s)
+    coarse = torch.randn(gz, gy, gx, device="cuda")
+    image = torch.empty(256, 512, 512, device="cuda")
+    fn = lambda: bsi.bsi_forward_scalar(coarse, dims_s, sp_s, image)
+    fn()
+    ms = median(time_events(torch, fn, 20))
+    Vs = 512 * 512 * 256
+    ex["scalar_upsample_512x512x256_x4"] = {"ms": round(ms, 4), "gvoxel_s": round(Vs / ms / 1e6, 2),
+                                            "hbm_frac": round((4 * Vs + 4 * gx * gy * gz) / ms / 1e6 / HBM_PEAK_GBS, 4)}
+    log("scalar upsampling:", ex["scalar_upsample_512x512x256_x4"])
+    del coarse, image
 
     # one SSD registration iteration at 256 x 256 x 160 (moving image made on the GPU)
     c = workloads.cfg4()

@@ -72,6 +72,18 @@ int32_t bsi_grid_dims(const int32_t dims[3], const int32_t spacing[3], int32_t o
 int32_t bsi_forward(const float* grid, const int32_t dims[3], const int32_t spacing[3],
                     float* field, hipStream_t stream);
 
+/* Scalar forward BSI: Eq. 1 with one value per control point, e.g. the pixels
+   of a coarse image as control points, giving its cubic B-spline upsampling by
+   the integer factors `spacing` ("image zooming", the other use of BSI named
+   in Sec. 8).  image[z][y][x] = sum B_l(u) B_m(v) B_n(w) grid[k+n][j+m][i+l].
+   grid: float [gz][gy][gx] read-only; image: float [nz][ny][nx] fully
+   overwritten.  Each value equals, bit for bit, the same component of
+   bsi_forward on a grid holding these values in that component.  For a 2-D
+   image use nz = 1 and spacing[2] = 1 (the grid then needs gz = 4 planes).
+   Errors: INVALID_ARG, UNSUPPORTED, NO_DEVICE, HIP. */
+int32_t bsi_forward_scalar(const float* grid, const int32_t dims[3], const int32_t spacing[3],
+                           float* image, hipStream_t stream);
+
 /* Scratch size in bytes that bsi_adjoint needs for this geometry (host-only). */
 int32_t bsi_adjoint_workspace_size(const int32_t dims[3], const int32_t spacing[3],
                                    size_t* bytes);

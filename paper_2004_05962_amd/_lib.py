@@ -25,7 +25,8 @@ BSI_ERR_NOMEM = -5
 BSI_MAX_SPACING = 64
 
 EXPORTS = (
-    "bsi_version", "bsi_last_error", "bsi_grid_dims", "bsi_forward", "bsi_adjoint_workspace_size",
+    "bsi_version", "bsi_last_error", "bsi_grid_dims", "bsi_forward", "bsi_forward_scalar",
+    "bsi_adjoint_workspace_size",
     "bsi_adjoint", "bsi_adjoint_partials", "bsi_adjoint_reduce", "bsi_warp", "bsi_ssd_workspace_size", "bsi_ssd_grad", "bsi_ssd_fused_workspace_size", "bsi_ssd_fused",
     "bsi_descent_step",
     "bsi_batch_create", "bsi_batch_bind", "bsi_batch_tune", "bsi_batch_config", "bsi_batch_run",
@@ -59,6 +60,7 @@ def lib():
         "bsi_last_error": ([], ctypes.c_char_p),
         "bsi_grid_dims": ([p3, p3, p3], i32),
         "bsi_forward": ([_VP, p3, p3, _VP, _VP], i32),
+        "bsi_forward_scalar": ([_VP, p3, p3, _VP, _VP], i32),
         "bsi_adjoint_workspace_size": ([p3, p3, ctypes.POINTER(sz)], i32),
         "bsi_adjoint": ([_VP, p3, p3, _VP, _VP, sz, _VP], i32),
         "bsi_adjoint_partials": ([_VP, p3, p3, _VP, sz, _VP], i32),
@@ -160,6 +162,29 @@ def bsi_forward(grid, dims, spacing, field, stream=None):
     g = _ptr(grid, "grid", grid_shape(dims, spacing))
     f = _ptr(field, "field", field_shape(dims))
     _check(lib().bsi_forward(g, _triple(dims, "dims"), _triple(spacing, "spacing"), f, _stream(stream)))
+
+
+def bsi_forward_scalar(grid, dims, spacing, image, stream=None):
+    """Scalar Eq. 1 (B-spline upsampling): ``image`` (nz, ny, nx) from ``grid`` (gz, gy, gx)."""
+    gx, gy, gz = bsi_grid_dims(dims, spacing)
+    nx, ny, nz = (int(v) for v in dims)
+    g = _ptr(grid, "grid", (gz, gy, gx))
+    o = _ptr(image, "image", (nz, ny, nx))
+    _check(lib().bsi_forward_scalar(g, _triple(dims, "dims"), _triple(spacing, "spacing"), o, _stream(stream)))
+
+
+def upsample(grid, spacing, dims=None, out=None, stream=None):
+    """Cubic B-spline upsampling of a coarse scalar volume ``grid`` (gz, gy, gx) by the
+    integer factors ``spacing`` (x, y, z); ``dims`` defaults to the largest volume
+    the grid covers, (g - 3) * spacing per axis."""
+    gz, gy, gx = (int(v) for v in grid.shape)
+    if dims is None:
+        dims = tuple((g - 3) * int(d) for g, d in zip((gx, gy, gz), spacing))
+    if out is None:
+        nx, ny, nz = (int(v) for v in dims)
+        out = torch.empty((nz, ny, nx), dtype=torch.float32, device=grid.device)
+    bsi_forward_scalar(grid, dims, spacing, out, stream)
+    return out
 
 
 def bsi_adjoint_workspace_size(dims, spacing):

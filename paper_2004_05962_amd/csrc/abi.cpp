@@ -143,6 +143,20 @@ int32_t bsi_forward(const float* grid, const int32_t dims[3], const int32_t spac
   return e == hipSuccess ? BSI_OK : hip_fail(e, "launching the forward kernel");
 }
 
+int32_t bsi_forward_scalar(const float* grid, const int32_t dims[3], const int32_t spacing[3], float* image,
+                           hipStream_t stream) {
+  clear_error();
+  VolGeom g;
+  int32_t rc = make_geom(dims, spacing, &g);
+  if (rc) return rc;
+  if (!grid) return null_arg("grid");
+  if (!image) return null_arg("image");
+  const float* lut = nullptr;
+  if ((rc = device_lut(&lut))) return rc;
+  hipError_t e = launch_forward_scalar(grid, image, g, lut, stream);
+  return e == hipSuccess ? BSI_OK : hip_fail(e, "launching the scalar forward kernel");
+}
+
 int32_t bsi_adjoint_workspace_size(const int32_t dims[3], const int32_t spacing[3], size_t* bytes) {
   clear_error();
   if (!bytes) {

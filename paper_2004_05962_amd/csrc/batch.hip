@@ -92,7 +92,7 @@ __device__ __forceinline__ Slice make_slice(int64_t total, int chunked) {
 __global__ __launch_bounds__(kFwdThreads) void batch_fwd_kernel(const VolDesc* __restrict__ vols, int count,
                                                                  int64_t total, int chunked,
                                                                  const float* __restrict__ lut) {
-  __shared__ FwdSmem sm;
+  __shared__ FwdSmem<3> sm;
   const Slice s = make_slice(total, chunked);
   for (int64_t item = s.begin; item < s.end; item += s.step) {
     const int vi = uniform(find_volume(vols, count, item, kFwd));
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kFwdThreads) void batch_fwd_kernel(const VolDesc* _
     const int bz = id / L.nby;
     const int z0 = bz * L.zchunk;
     const int z1 = min(g.nz, z0 + L.zchunk);
-    fwd_block(d.grid, d.field, g, lut, bx * kWave, by * kFwdRows, z0, z1, sm, threadIdx.x);
+    fwd_block<3>(d.grid, d.field, g, lut, bx * kWave, by * kFwdRows, z0, z1, sm, threadIdx.x);
   }
 }
 

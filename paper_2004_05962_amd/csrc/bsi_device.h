@@ -72,16 +72,6 @@ __device__ __forceinline__ int xcd_remap(int id, int n) {
 __device__ __forceinline__ F3 ldf3(const float* p) { return *reinterpret_cast<const F3*>(p); }
 __device__ __forceinline__ void stf3(float* p, F3 v) { *reinterpret_cast<F3*>(p) = v; }
 
-// Streaming store of the dense field: non-temporal, so the write stream does not
-// evict the control points that neighbouring waves still read from L2.
-// (12-byte stores straight from the lanes measured faster than staging the
-// wave's row through LDS into 16-byte stores.)
-__device__ __forceinline__ void stf3_stream(float* p, F3 v) {
-  __builtin_nontemporal_store(v.x, p);
-  __builtin_nontemporal_store(v.y, p + 1);
-  __builtin_nontemporal_store(v.z, p + 2);
-}
-
 // ----------------------------------------------------------------------------
 // Forward BSI for one workgroup: kFwdRows consecutive rows y0.. of the 64-voxel
 // x-strip x0..x0+63 (lane = x), voxel planes z0..z1-1.  All bounds are
@@ -107,83 +97,107 @@ constexpr int kFwdRows = BSI_FWD_ROWS;                 // waves (rows) per workg
 constexpr int kFwdThreads = kWave * kFwdRows;
 constexpr int kFwdMaxCx = (kWave - 1) + 4;             // window width at spacing 1
 constexpr int kFwdMaxCy = (kFwdRows - 1) + 4;          // window height at spacing 1
-constexpr int kFwdPitch = kFwdMaxCx * 3;               // floats per staged control row
-constexpr int kFwdPlane = kFwdMaxCy * kFwdPitch;       // floats per staged plane
-constexpr int kFwdLoads = (kFwdPlane + kFwdThreads - 1) / kFwdThreads;
+// Staged window of one control plane for C components per point.
+template <int C>
+__host__ __device__ constexpr int fwd_pitch() { return kFwdMaxCx * C; }  // floats per staged control row
+template <int C>
+__host__ __device__ constexpr int fwd_loads() {  // staged floats per thread
+  return (kFwdMaxCy * fwd_pitch<C>() + kFwdThreads - 1) / kFwdThreads;
+}
 
+template <int C>
 struct FwdSmem {
-  float ring[2][kFwdLoads * kFwdThreads];
+  float ring[2][fwd_loads<C>() * kFwdThreads];
 };
 
 // Staging map: thread tid moves floats e = tid + k * kFwdThreads of the window,
-// e = row * kFwdPitch + col; goff[k] is its grid offset within a plane, or -1
-// when e lies outside this workgroup's window.
+// e = row * pitch + col; goff[k] is its grid offset within a plane, or -1 when
+// e lies outside this workgroup's window.
+template <int C>
 struct FwdStage {
-  int goff[kFwdLoads];
+  int goff[fwd_loads<C>()];
 };
 
-__device__ __forceinline__ FwdStage fwd_stage_map(const VolGeom& g, int cx0, int ncx, int cy0, int ncy, int tid) {
-  FwdStage m;
+template <int C>
+__device__ __forceinline__ FwdStage<C> fwd_stage_map(const VolGeom& g, int cx0, int ncx, int cy0, int ncy,
+                                                     int tid) {
+  FwdStage<C> m;
 #pragma unroll
-  for (int k = 0; k < kFwdLoads; ++k) {
+  for (int k = 0; k < fwd_loads<C>(); ++k) {
     const int e = tid + k * kFwdThreads;
-    const int row = e / kFwdPitch;
-    const int col = e - row * kFwdPitch;
-    m.goff[k] = (row < ncy && col < ncx * 3) ? ((cy0 + row) * g.gx + cx0) * 3 + col : -1;
+    const int row = e / fwd_pitch<C>();
+    const int col = e - row * fwd_pitch<C>();
+    m.goff[k] = (row < ncy && col < ncx * C) ? ((cy0 + row) * g.gx + cx0) * C + col : -1;
   }
   return m;
 }
 
-__device__ __forceinline__ void fwd_fetch(const float* __restrict__ grid, const VolGeom& g, const FwdStage& m,
-                                          int cz, float (&r)[kFwdLoads]) {
-  const float* plane = grid + (size_t)cz * g.gy * g.gx * 3;
+template <int C>
+__device__ __forceinline__ void fwd_fetch(const float* __restrict__ grid, const VolGeom& g,
+                                          const FwdStage<C>& m, int cz, float (&r)[fwd_loads<C>()]) {
+  const float* plane = grid + (size_t)cz * g.gy * g.gx * C;
 #pragma unroll
-  for (int k = 0; k < kFwdLoads; ++k) r[k] = m.goff[k] >= 0 ? plane[m.goff[k]] : 0.f;
+  for (int k = 0; k < fwd_loads<C>(); ++k) r[k] = m.goff[k] >= 0 ? plane[m.goff[k]] : 0.f;
 }
 
-__device__ __forceinline__ void fwd_stage(float* __restrict__ slot, int tid, const float (&r)[kFwdLoads]) {
+template <int C>
+__device__ __forceinline__ void fwd_stage(float* __restrict__ slot, int tid, const float (&r)[fwd_loads<C>()]) {
 #pragma unroll
-  for (int k = 0; k < kFwdLoads; ++k) slot[tid + k * kFwdThreads] = r[k];
+  for (int k = 0; k < fwd_loads<C>(); ++k) slot[tid + k * kFwdThreads] = r[k];
 }
+
+template <int C>
+struct FwdVal {
+  float v[C];
+};
 
 // Q for this lane's (x, y) from a staged plane: the x-contraction of each of the
 // 4 control rows, then the y-contraction with weights wy[0..3].  The row loop is
-// kept rolled so only one row (12 values) is in flight: a small register
-// footprint, i.e. more waves per SIMD to hide LDS and memory latency.
-__device__ __forceinline__ F3 fwd_contract(const float* __restrict__ slot, int base, float bx0, float bx1,
-                                           float bx2, float bx3, const float* __restrict__ wy) {
-  F3 q{0.f, 0.f, 0.f};
+// kept rolled so only one row is in flight: a small register footprint, i.e.
+// more waves per SIMD to hide LDS and memory latency.
+template <int C>
+__device__ __forceinline__ FwdVal<C> fwd_contract(const float* __restrict__ slot, int base, float bx0,
+                                                  float bx1, float bx2, float bx3,
+                                                  const float* __restrict__ wy) {
+  FwdVal<C> q;
+#pragma unroll
+  for (int c = 0; c < C; ++c) q.v[c] = 0.f;
 #pragma unroll 1
   for (int m = 0; m < 4; ++m) {
-    const float* p = slot + base + m * kFwdPitch;
-    const float rx = fmaf(bx3, p[9], fmaf(bx2, p[6], fmaf(bx1, p[3], bx0 * p[0])));
-    const float ry = fmaf(bx3, p[10], fmaf(bx2, p[7], fmaf(bx1, p[4], bx0 * p[1])));
-    const float rz = fmaf(bx3, p[11], fmaf(bx2, p[8], fmaf(bx1, p[5], bx0 * p[2])));
+    const float* p = slot + base + m * fwd_pitch<C>();
     const float b = wy[m];
-    if (m == 0) {
-      q.x = b * rx;
-      q.y = b * ry;
-      q.z = b * rz;
-    } else {
-      q.x = fmaf(b, rx, q.x);
-      q.y = fmaf(b, ry, q.y);
-      q.z = fmaf(b, rz, q.z);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const float r = fmaf(bx3, p[3 * C + c], fmaf(bx2, p[2 * C + c], fmaf(bx1, p[C + c], bx0 * p[c])));
+      q.v[c] = m == 0 ? b * r : fmaf(b, r, q.v[c]);
     }
   }
   return q;
 }
 
+// Streaming store of one voxel's C values: non-temporal, so the write stream
+// does not evict the control points that neighbouring waves still read from L2.
+// (12-byte stores straight from the lanes measured faster than staging the
+// wave's row through LDS into 16-byte stores.)
+template <int C>
+__device__ __forceinline__ void fwd_store(float* p, const float (&t)[C]) {
+#pragma unroll
+  for (int c = 0; c < C; ++c) __builtin_nontemporal_store(t[c], p + c);
+}
+
 // Collective over the workgroup (kFwdThreads threads, all bounds uniform).
+// C = 3 for displacement grids, C = 1 for scalar images.
+template <int C>
 __device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float* __restrict__ field,
                                           const VolGeom& g, const float* __restrict__ lut, int x0, int y0,
-                                          int z0, int z1, FwdSmem& sm, int tid) {
+                                          int z0, int z1, FwdSmem<C>& sm, int tid) {
   const int lane = tid & (kWave - 1);
   const int wave = uniform(tid / kWave);
   const int cx0 = x0 / g.dx;
   const int ncx = (min(x0 + kWave, g.nx) - 1) / g.dx - cx0 + 4;
   const int cy0 = y0 / g.dy;
   const int ncy = (min(y0 + kFwdRows, g.ny) - 1) / g.dy - cy0 + 4;
-  const FwdStage map = fwd_stage_map(g, cx0, ncx, cy0, ncy, tid);
+  const FwdStage<C> map = fwd_stage_map<C>(g, cx0, ncx, cy0, ncy, tid);
 
   const int x = x0 + lane;
   const int y = y0 + wave;
@@ -197,55 +211,56 @@ __device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float*
   const float* wx = lut_row(lut, g.dx, ox);
   const float bx0 = wx[0], bx1 = wx[1], bx2 = wx[2], bx3 = wx[3];
   const float* wy = lut_row(lut, g.dy, oy);  // wave-uniform
-  const int base = (ty - cy0) * kFwdPitch + (tx - cx0) * 3;
+  const int base = (ty - cy0) * fwd_pitch<C>() + (tx - cx0) * C;
 
   int tz = z0 / g.dz;
   int oz = z0 - tz * g.dz;
-  float r[kFwdLoads];
+  float r[fwd_loads<C>()];
   // Warm-up: stage planes tz, tz+1, tz+2 one at a time (slots 0, 1, 0) and shift
   // their contractions into q0..q2; then stage plane tz+3 into slot 1 (its
   // contraction is the loop head).  One plane in flight keeps registers low.
-  F3 q0{0.f, 0.f, 0.f}, q1{0.f, 0.f, 0.f}, q2{0.f, 0.f, 0.f};
+  FwdVal<C> q0, q1, q2;
+#pragma unroll
+  for (int c = 0; c < C; ++c) q0.v[c] = q1.v[c] = q2.v[c] = 0.f;
 #pragma unroll 1
   for (int j = 0; j < 3; ++j) {
     __syncthreads();  // the slot may still be read (previous item or iteration)
-    fwd_fetch(grid, g, map, tz + j, r);
-    fwd_stage(sm.ring[j & 1], tid, r);
+    fwd_fetch<C>(grid, g, map, tz + j, r);
+    fwd_stage<C>(sm.ring[j & 1], tid, r);
     __syncthreads();
-    const F3 qn = fwd_contract(sm.ring[j & 1], base, bx0, bx1, bx2, bx3, wy);
+    const FwdVal<C> qn = fwd_contract<C>(sm.ring[j & 1], base, bx0, bx1, bx2, bx3, wy);
     q0 = q1;
     q1 = q2;
     q2 = qn;
   }
   __syncthreads();
-  fwd_fetch(grid, g, map, tz + 3, r);
-  fwd_stage(sm.ring[1], tid, r);
+  fwd_fetch<C>(grid, g, map, tz + 3, r);
+  fwd_stage<C>(sm.ring[1], tid, r);
   __syncthreads();
   int slot3 = 1;  // slot holding plane tz + 3
 
-  const size_t zstride = (size_t)g.ny * g.nx * 3;
-  float* out = field + (((size_t)z0 * g.ny + yc) * g.nx + xc) * 3;
+  const size_t zstride = (size_t)g.ny * g.nx * C;
+  float* out = field + (((size_t)z0 * g.ny + yc) * g.nx + xc) * C;
   int z = z0;
   for (;;) {
-    const F3 q3 = fwd_contract(sm.ring[slot3], base, bx0, bx1, bx2, bx3, wy);
+    const FwdVal<C> q3 = fwd_contract<C>(sm.ring[slot3], base, bx0, bx1, bx2, bx3, wy);
     const int left = z1 - z;
     const bool more = g.dz - oz < left;  // another tile follows inside this range
     // its new plane tz + 4 is then at most ceil(nz/dz) + 2 = gz - 1: in bounds
-    if (more) fwd_fetch(grid, g, map, tz + 4, r);
+    if (more) fwd_fetch<C>(grid, g, map, tz + 4, r);
     const int oend = more ? g.dz : oz + left;
     for (; oz < oend; ++oz, ++z) {
       const float* wz = lut_row(lut, g.dz, oz);
       const float w0 = wz[0], w1 = wz[1], w2 = wz[2], w3 = wz[3];
-      F3 t;
-      t.x = fmaf(w3, q3.x, fmaf(w2, q2.x, fmaf(w1, q1.x, w0 * q0.x)));
-      t.y = fmaf(w3, q3.y, fmaf(w2, q2.y, fmaf(w1, q1.y, w0 * q0.y)));
-      t.z = fmaf(w3, q3.z, fmaf(w2, q2.z, fmaf(w1, q1.z, w0 * q0.z)));
-      if (active) stf3_stream(out, t);
+      float t[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) t[c] = fmaf(w3, q3.v[c], fmaf(w2, q2.v[c], fmaf(w1, q1.v[c], w0 * q0.v[c])));
+      if (active) fwd_store<C>(out, t);
       out += zstride;
     }
     if (!more) break;
     // plane tz + 4 goes to the slot of plane tz + 2, consumed one tile ago
-    fwd_stage(sm.ring[slot3 ^ 1], tid, r);
+    fwd_stage<C>(sm.ring[slot3 ^ 1], tid, r);
     __syncthreads();
     slot3 ^= 1;
     oz = 0;

@@ -39,6 +39,8 @@ FwdLaunch make_fwd_launch(const VolGeom& g);
 
 hipError_t launch_forward(const float* grid, float* field, const VolGeom& g, const float* lut,
                           hipStream_t s);
+hipError_t launch_forward_scalar(const float* grid, float* image, const VolGeom& g, const float* lut,
+                                 hipStream_t s);
 hipError_t launch_adjoint(const float* dfield, float* grad, const AdjGeom& a, const float* lut,
                           float* part, hipStream_t s);
 hipError_t launch_adjoint_partials(const float* dfield, const AdjGeom& a, const float* lut, float* part,

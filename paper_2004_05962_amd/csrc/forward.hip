@@ -1,4 +1,5 @@
-// Forward BSI kernel (Eq. 1) for one volume.
+// Forward BSI kernel (Eq. 1) for one volume: C = 3 for a displacement grid,
+// C = 1 for a scalar image (B-spline upsampling).
 //
 // Workgroup = kFwdRows waves = kFwdRows consecutive rows of one 64-voxel x-strip,
 // over one chunk of z; it runs fwd_block (bsi_device.h): per-lane sum
@@ -10,10 +11,11 @@
 
 namespace bsi {
 
+template <int C>
 __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(const float* __restrict__ grid,
                                                            float* __restrict__ field, VolGeom g,
                                                            const float* __restrict__ lut, FwdLaunch L) {
-  __shared__ FwdSmem sm;
+  __shared__ FwdSmem<C> sm;
   int id = xcd_remap(blockIdx.x, gridDim.x);
   const int bx = id % L.nbx;
   id /= L.nbx;
@@ -21,7 +23,7 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(const float* __restric
   const int bz = id / L.nby;
   const int z0 = bz * L.zchunk;
   const int z1 = min(g.nz, z0 + L.zchunk);
-  fwd_block(grid, field, g, lut, bx * kWave, by * kFwdRows, z0, z1, sm, threadIdx.x);
+  fwd_block<C>(grid, field, g, lut, bx * kWave, by * kFwdRows, z0, z1, sm, threadIdx.x);
 }
 
 FwdLaunch make_fwd_launch(const VolGeom& g) {
@@ -45,7 +47,16 @@ hipError_t launch_forward(const float* grid, float* field, const VolGeom& g, con
                           hipStream_t s) {
   const FwdLaunch L = make_fwd_launch(g);
   const long blocks = (long)L.nbx * L.nby * L.nbz;
-  hipLaunchKernelGGL(fwd_kernel, dim3((unsigned)blocks), dim3(kFwdThreads), 0, s, grid, field, g,
+  hipLaunchKernelGGL(fwd_kernel<3>, dim3((unsigned)blocks), dim3(kFwdThreads), 0, s, grid, field, g,
+                     lut, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward_scalar(const float* grid, float* image, const VolGeom& g, const float* lut,
+                                 hipStream_t s) {
+  const FwdLaunch L = make_fwd_launch(g);
+  const long blocks = (long)L.nbx * L.nby * L.nbz;
+  hipLaunchKernelGGL(fwd_kernel<1>, dim3((unsigned)blocks), dim3(kFwdThreads), 0, s, grid, image, g,
                      lut, L);
   return hipGetLastError();
 }
