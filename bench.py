@@ -19,7 +19,8 @@ Printed as ONE JSON line on stdout (logs go to stderr), with:
                 graph launch against per-volume launches, and one SSD
                 registration iteration at 256 x 256 x 160, fused (one pass,
                 no field in memory) and unfused (forward, SSD, adjoint), and
-                scalar B-spline upsampling to 512 x 512 x 256 (factor 4).
+                scalar B-spline upsampling to 512 x 512 x 256 (factor 4), and
+                the forward in the paper's lerp form (ablation).
 """
 import argparse
 import hashlib
@@ -346,6 +347,23 @@ def run_extras(torch, bsi, workloads):
     log("batched:", ex["batched_32_volumes"])
     plan.close()
     del grids, dfields, fields, grads
+
+    # the paper's lerp form of the forward (ablation): 63 lerps (a subtraction and
+    # an FMA each, 3 flops) per component and voxel, against about 22 FMA for the
+    # sum-factorised kernel
+    field_l = torch.empty(256, 512, 512, 3, device="cuda")
+    c2 = workloads.cfg2(5)
+    grid_l = torch.from_numpy(c2["grid"]).cuda()
+    fn = lambda: bsi.bsi_forward_lerp(grid_l, c2["dims"], c2["spacing"], field_l)
+    fn()
+    ms = median(time_events(torch, fn, 10))
+    Vl = 512 * 512 * 256
+    flops = Vl * 63 * 3 * 3
+    ex["forward_lerp_form_512x512x256_d5"] = {
+        "ms": round(ms, 4), "gvoxel_s": round(Vl / ms / 1e6, 2),
+        "tflops": round(flops / ms / 1e9, 2), "frac_fp32_vector_peak": round(flops / ms / 1e9 / 157.3, 4)}
+    log("forward lerp form:", ex["forward_lerp_form_512x512x256_d5"])
+    del field_l, grid_l
 
     # scalar B-spline upsampling: a 131 x 131 x 67 coarse volume (control points)
     # to 512 x 512 x 256 voxels, factor 4 on every axis

@@ -72,6 +72,16 @@ int32_t bsi_grid_dims(const int32_t dims[3], const int32_t spacing[3], int32_t o
 int32_t bsi_forward(const float* grid, const int32_t dims[3], const int32_t spacing[3],
                     float* field, hipStream_t stream);
 
+/* Forward BSI evaluated in the paper's lerp form (Sec. 3.3, App. B): per voxel,
+   8 trilinear interpolations of the 2x2x2 sub-cubes of its 4x4x4 window with
+   h0 = B1/(B0+B1), h1 = B3/(B2+B3), then one of the 8 results with
+   g1 = B2+B3.  Same result as bsi_forward up to FP32 rounding, with about
+   15 times its arithmetic: an ablation of the paper's evaluation against the
+   sum-factorised kernel, not a faster path.  Arguments and errors as in
+   bsi_forward. */
+int32_t bsi_forward_lerp(const float* grid, const int32_t dims[3], const int32_t spacing[3],
+                         float* field, hipStream_t stream);
+
 /* Scalar forward BSI: Eq. 1 with one value per control point, e.g. the pixels
    of a coarse image as control points, giving its cubic B-spline upsampling by
    the integer factors `spacing` ("image zooming", the other use of BSI named

@@ -25,7 +25,7 @@ BSI_ERR_NOMEM = -5
 BSI_MAX_SPACING = 64
 
 EXPORTS = (
-    "bsi_version", "bsi_last_error", "bsi_grid_dims", "bsi_forward", "bsi_forward_scalar",
+    "bsi_version", "bsi_last_error", "bsi_grid_dims", "bsi_forward", "bsi_forward_lerp", "bsi_forward_scalar",
     "bsi_adjoint_workspace_size",
     "bsi_adjoint", "bsi_adjoint_partials", "bsi_adjoint_reduce", "bsi_warp", "bsi_ssd_workspace_size", "bsi_ssd_grad", "bsi_ssd_fused_workspace_size", "bsi_ssd_fused",
     "bsi_descent_step",
@@ -61,6 +61,7 @@ def lib():
         "bsi_grid_dims": ([p3, p3, p3], i32),
         "bsi_forward": ([_VP, p3, p3, _VP, _VP], i32),
         "bsi_forward_scalar": ([_VP, p3, p3, _VP, _VP], i32),
+        "bsi_forward_lerp": ([_VP, p3, p3, _VP, _VP], i32),
         "bsi_adjoint_workspace_size": ([p3, p3, ctypes.POINTER(sz)], i32),
         "bsi_adjoint": ([_VP, p3, p3, _VP, _VP, sz, _VP], i32),
         "bsi_adjoint_partials": ([_VP, p3, p3, _VP, sz, _VP], i32),
@@ -162,6 +163,13 @@ def bsi_forward(grid, dims, spacing, field, stream=None):
     g = _ptr(grid, "grid", grid_shape(dims, spacing))
     f = _ptr(field, "field", field_shape(dims))
     _check(lib().bsi_forward(g, _triple(dims, "dims"), _triple(spacing, "spacing"), f, _stream(stream)))
+
+
+def bsi_forward_lerp(grid, dims, spacing, field, stream=None):
+    """Eq. 1 in the paper's lerp form (ablation; same result up to rounding, far more arithmetic)."""
+    g = _ptr(grid, "grid", grid_shape(dims, spacing))
+    f = _ptr(field, "field", field_shape(dims))
+    _check(lib().bsi_forward_lerp(g, _triple(dims, "dims"), _triple(spacing, "spacing"), f, _stream(stream)))
 
 
 def bsi_forward_scalar(grid, dims, spacing, image, stream=None):

@@ -143,6 +143,22 @@ int32_t bsi_forward(const float* grid, const int32_t dims[3], const int32_t spac
   return e == hipSuccess ? BSI_OK : hip_fail(e, "launching the forward kernel");
 }
 
+int32_t bsi_forward_lerp(const float* grid, const int32_t dims[3], const int32_t spacing[3], float* field,
+                         hipStream_t stream) {
+  clear_error();
+  VolGeom g;
+  int32_t rc = make_geom(dims, spacing, &g);
+  if (rc) return rc;
+  if (!grid) return null_arg("grid");
+  if (!field) return null_arg("field");
+  int dev = 0;
+  if ((rc = current_device(&dev))) return rc;
+  const float* lut = nullptr;
+  if ((rc = lerp_lut_device_ptr(dev, &lut))) return rc;
+  hipError_t e = launch_forward_lerp(grid, field, g, lut, stream);
+  return e == hipSuccess ? BSI_OK : hip_fail(e, "launching the lerp-form forward kernel");
+}
+
 int32_t bsi_forward_scalar(const float* grid, const int32_t dims[3], const int32_t spacing[3], float* image,
                            hipStream_t stream) {
   clear_error();

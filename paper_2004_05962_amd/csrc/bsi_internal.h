@@ -21,6 +21,8 @@ int32_t current_device(int* dev);
 // Basis table of every spacing 1..kMaxSpacing on device `dev` (uploaded on the
 // first call per device, then cached for the life of the process).
 int32_t lut_device_ptr(int dev, const float** out);
+// Lerp-form weights (h0, h1, g1, 0) per offset, same row layout (lut_row).
+int32_t lerp_lut_device_ptr(int dev, const float** out);
 
 // Host-side geometry helpers.
 int32_t make_geom(const int32_t dims[3], const int32_t spacing[3], VolGeom* g);
@@ -41,6 +43,8 @@ hipError_t launch_forward(const float* grid, float* field, const VolGeom& g, con
                           hipStream_t s);
 hipError_t launch_forward_scalar(const float* grid, float* image, const VolGeom& g, const float* lut,
                                  hipStream_t s);
+hipError_t launch_forward_lerp(const float* grid, float* field, const VolGeom& g, const float* lerp_lut,
+                               hipStream_t s);
 hipError_t launch_adjoint(const float* dfield, float* grad, const AdjGeom& a, const float* lut,
                           float* part, hipStream_t s);
 hipError_t launch_adjoint_partials(const float* dfield, const AdjGeom& a, const float* lut, float* part,

@@ -79,6 +79,10 @@ def test_null_pointers_rejected_before_device():
     d, s = _t((8, 8, 8)), _t((2, 2, 2))
     assert _call("bsi_forward", NULL, d, s, P, NULL) == _lib.BSI_ERR_INVALID_ARG
     assert _call("bsi_forward", P, d, s, NULL, NULL) == _lib.BSI_ERR_INVALID_ARG
+    for name in ("bsi_forward_lerp", "bsi_forward_scalar"):
+        assert _call(name, NULL, d, s, P, NULL) == _lib.BSI_ERR_INVALID_ARG
+        assert _call(name, P, d, s, NULL, NULL) == _lib.BSI_ERR_INVALID_ARG
+        assert _call(name, P, d, _t((0, 1, 1)), P, NULL) == _lib.BSI_ERR_INVALID_ARG
     assert _call("bsi_adjoint", P, d, s, P, NULL, 1 << 30, NULL) == _lib.BSI_ERR_INVALID_ARG
     assert _call("bsi_adjoint_partials", NULL, d, s, P, 1 << 30, NULL) == _lib.BSI_ERR_INVALID_ARG
     assert _call("bsi_adjoint_partials", P, d, s, NULL, 1 << 30, NULL) == _lib.BSI_ERR_INVALID_ARG
@@ -134,3 +138,9 @@ def test_workspace_sizes_follow_brick_geometry():
     for dims, sp in (((512, 512, 256), (5, 5, 5)), ((256, 256, 256), (5, 5, 5)), ((512, 512, 256), (8, 8, 8))):
         field_bytes = 12 * dims[0] * dims[1] * dims[2]
         assert bsi.bsi_adjoint_workspace_size(dims, sp) < 0.06 * field_bytes
+
+
+def test_every_export_has_a_package_binding():
+    """Each C entry point is callable from the package under the same name."""
+    missing = [n for n in _lib.EXPORTS if not callable(getattr(bsi, n, None))]
+    assert not missing, missing

@@ -126,3 +126,16 @@ def test_rejects_bad_tensors():
         bsi.forward(g.double(), dims, spacing)
     with pytest.raises(ValueError):
         bsi.forward(g.cpu(), dims, spacing)
+
+
+@pytest.mark.parametrize("dims,spacing", CASES)
+def test_lerp_form_matches_oracle(dims, spacing):
+    """The lerp-form kernel (Sec. 3.3 / App. B) against the direct FP64 sum and
+    the oracle's own lerp form, at the forward's bar."""
+    say("forward lerp form", dims, spacing)
+    grid = workloads.random_grid(dims, spacing, 2.0, seed=300 + sum(dims) + 7 * sum(spacing))
+    out = torch.empty(bsi.field_shape(dims), device="cuda")
+    bsi.bsi_forward_lerp(dev(grid), dims, spacing, out)
+    got = host(out)
+    assert max_abs(got, oracle.forward(grid, dims, spacing)) <= _tol(grid)
+    assert max_abs(got, oracle.forward_lerp(grid, dims, spacing)) <= _tol(grid)
