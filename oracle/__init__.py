@@ -156,4 +156,4 @@ def adjoint_points(dfield, dims, spacing, cps) -> np.ndarray:
     return out
 
 
-from . import brute, warp, registration, scalar  # noqa: E402,F401
+from . import brute, general, warp, registration, scalar  # noqa: E402,F401
