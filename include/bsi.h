@@ -133,6 +133,42 @@ int32_t bsi_adjoint_reduce(const void* workspace, size_t workspace_bytes,
                            float* grid_grad, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Control grids with real spacing and an origin offset (the paper's method
+ * needs the grid aligned to the voxels with integer spacing, Sec. 3.4; Sec. 8
+ * names this as its limitation).  Per axis a, with spacing[a] = s >= 1 and
+ * origin[a] = o, -s < o <= 0 (host float arrays):
+ *   control point (storage index) c sits at voxel o + (c - 1) s;
+ *   voxel x reads c = i .. i+3, i = floor(t), weights B_l(t - i), t = (x - o)/s,
+ *   with t formed in FP64 from the float values of s and o;
+ *   the grid has g = floor((n - 1 - o)/s) + 4 points (ceil(n/s) + 3 for
+ *   integer s and o = 0, where these calls compute the same map as
+ *   bsi_forward / bsi_adjoint, up to FP32 rounding).
+ * Weights are evaluated per coordinate instead of per in-tile offset.
+ * ------------------------------------------------------------------------- */
+
+/* Control-grid size out_g[a] for this geometry (host-only).
+   Errors: INVALID_ARG (s < 1, o outside (-s, 0], n < 1), UNSUPPORTED. */
+int32_t bsi_general_grid_dims(const int32_t dims[3], const float spacing[3], const float origin[3],
+                              int32_t out_g[3]);
+
+/* Forward (Eq. 1) on the general grid.  grid: [gz][gy][gx][3]; field:
+   [nz][ny][nx][3] overwritten.  Errors as bsi_general_grid_dims, NO_DEVICE, HIP. */
+int32_t bsi_forward_general(const float* grid, const int32_t dims[3], const float spacing[3],
+                            const float origin[3], float* field, hipStream_t stream);
+
+/* Scratch bytes for bsi_adjoint_general (host-only). */
+int32_t bsi_adjoint_general_workspace_size(const int32_t dims[3], const float spacing[3],
+                                           const float origin[3], size_t* bytes);
+
+/* Adjoint of bsi_forward_general, grid_grad OVERWRITTEN: three separable
+   gathers (x, then y, then z) in a fixed order, no atomics.  workspace as for
+   bsi_adjoint, of bsi_adjoint_general_workspace_size() bytes.
+   Errors as bsi_forward_general (INVALID_ARG also for a small workspace). */
+int32_t bsi_adjoint_general(const float* dfield, const int32_t dims[3], const float spacing[3],
+                            const float origin[3], float* grid_grad, void* workspace,
+                            size_t workspace_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
  * SSD registration step (the FFD loop of Sec. 6 with a sum-of-squared-
  * differences similarity standing in for the paper's NiftyReg measure).
  * p(x) = x + T(x) in voxel units, formed in FP32; trilinear interpolation with

@@ -85,3 +85,17 @@ def adjoint(dfield, dims, spacing, origin):
                 np.add.at(grad, ((iz + n)[:, None, None], (iy + m)[None, :, None], (ix + l)[None, None, :]),
                           w[..., None] * d)
     return grad
+
+
+def forward_points(grid, dims, spacing, origin, pts):
+    """``forward`` at voxels pts[k] = (x, y, z) only: (k, 3), FP64."""
+    g = np.asarray(grid, dtype=np.float64)
+    p = np.asarray(pts, dtype=np.int64).reshape(-1, 3)
+    tabs = [axis_table(int(n), s, o) for n, s, o in zip(dims, spacing, origin)]
+    (ix, wx), (iy, wy), (iz, wz) = [(i[p[:, a]], w[p[:, a]]) for a, (i, w) in enumerate(tabs)]
+    out = np.zeros((p.shape[0], 3), np.float64)
+    for n in range(4):
+        for m in range(4):
+            for l in range(4):
+                out += (wz[:, n] * wy[:, m] * wx[:, l])[:, None] * g[iz + n, iy + m, ix + l]
+    return out

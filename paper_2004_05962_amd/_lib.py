@@ -27,7 +27,8 @@ BSI_MAX_SPACING = 64
 EXPORTS = (
     "bsi_version", "bsi_last_error", "bsi_grid_dims", "bsi_forward", "bsi_forward_lerp", "bsi_forward_scalar",
     "bsi_adjoint_workspace_size",
-    "bsi_adjoint", "bsi_adjoint_partials", "bsi_adjoint_reduce", "bsi_warp", "bsi_ssd_workspace_size", "bsi_ssd_grad", "bsi_ssd_fused_workspace_size", "bsi_ssd_fused",
+    "bsi_adjoint", "bsi_adjoint_partials", "bsi_adjoint_reduce", "bsi_general_grid_dims",
+    "bsi_forward_general", "bsi_adjoint_general_workspace_size", "bsi_adjoint_general", "bsi_warp", "bsi_ssd_workspace_size", "bsi_ssd_grad", "bsi_ssd_fused_workspace_size", "bsi_ssd_fused",
     "bsi_descent_step",
     "bsi_batch_create", "bsi_batch_bind", "bsi_batch_tune", "bsi_batch_config", "bsi_batch_run",
     "bsi_batch_run_separate", "bsi_batch_capture", "bsi_batch_launch", "bsi_batch_destroy",
@@ -55,6 +56,7 @@ def lib():
     L = ctypes.CDLL(LIB_PATH)
     i32, i64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     p3 = ctypes.POINTER(ctypes.c_int32)
+    pf3 = ctypes.POINTER(ctypes.c_float)
     sig = {
         "bsi_version": ([], i32),
         "bsi_last_error": ([], ctypes.c_char_p),
@@ -65,6 +67,10 @@ def lib():
         "bsi_adjoint_workspace_size": ([p3, p3, ctypes.POINTER(sz)], i32),
         "bsi_adjoint": ([_VP, p3, p3, _VP, _VP, sz, _VP], i32),
         "bsi_adjoint_partials": ([_VP, p3, p3, _VP, sz, _VP], i32),
+        "bsi_general_grid_dims": ([p3, pf3, pf3, p3], i32),
+        "bsi_forward_general": ([_VP, p3, pf3, pf3, _VP, _VP], i32),
+        "bsi_adjoint_general_workspace_size": ([p3, pf3, pf3, ctypes.POINTER(sz)], i32),
+        "bsi_adjoint_general": ([_VP, p3, pf3, pf3, _VP, _VP, sz, _VP], i32),
         "bsi_adjoint_reduce": ([_VP, sz, p3, p3, _VP, _VP], i32),
         "bsi_warp": ([_VP, _VP, p3, _VP, _VP], i32),
         "bsi_ssd_workspace_size": ([p3, ctypes.POINTER(sz)], i32),
@@ -232,6 +238,54 @@ def _workspace(workspace):
     if not isinstance(workspace, torch.Tensor) or workspace.device.type != "cuda" or not workspace.is_contiguous():
         raise ValueError("workspace must be a contiguous device tensor")
     return _raw(workspace), workspace.numel() * workspace.element_size()
+
+
+# ------------------------------------------------- real spacing, origin offset
+_F32x3 = ctypes.c_float * 3
+
+
+def _ftriple(v, name):
+    vals = [float(x) for x in v]
+    if len(vals) != 3:
+        raise ValueError(f"{name} must have 3 entries (x, y, z)")
+    return _F32x3(*vals)
+
+
+def bsi_general_grid_dims(dims, spacing, origin):
+    """(gx, gy, gz) = floor((n - 1 - o) / s) + 4 per axis."""
+    out = _I32x3()
+    _check(lib().bsi_general_grid_dims(_triple(dims, "dims"), _ftriple(spacing, "spacing"),
+                                       _ftriple(origin, "origin"), out))
+    return tuple(out)
+
+
+def general_grid_shape(dims, spacing, origin):
+    gx, gy, gz = bsi_general_grid_dims(dims, spacing, origin)
+    return (gz, gy, gx, 3)
+
+
+def bsi_forward_general(grid, dims, spacing, origin, field, stream=None):
+    """Eq. 1 for real spacing and an origin offset (control point c at o + (c - 1) s)."""
+    g = _ptr(grid, "grid", general_grid_shape(dims, spacing, origin))
+    f = _ptr(field, "field", field_shape(dims))
+    _check(lib().bsi_forward_general(g, _triple(dims, "dims"), _ftriple(spacing, "spacing"),
+                                     _ftriple(origin, "origin"), f, _stream(stream)))
+
+
+def bsi_adjoint_general_workspace_size(dims, spacing, origin):
+    n = ctypes.c_size_t()
+    _check(lib().bsi_adjoint_general_workspace_size(_triple(dims, "dims"), _ftriple(spacing, "spacing"),
+                                                    _ftriple(origin, "origin"), ctypes.byref(n)))
+    return int(n.value)
+
+
+def bsi_adjoint_general(dfield, dims, spacing, origin, grid_grad, workspace, stream=None):
+    """Transpose of bsi_forward_general; ``grid_grad`` overwritten."""
+    d = _ptr(dfield, "dfield", field_shape(dims))
+    g = _ptr(grid_grad, "grid_grad", general_grid_shape(dims, spacing, origin))
+    w, nbytes = _workspace(workspace)
+    _check(lib().bsi_adjoint_general(d, _triple(dims, "dims"), _ftriple(spacing, "spacing"),
+                                     _ftriple(origin, "origin"), g, w, nbytes, _stream(stream)))
 
 
 # ---------------------------------------------------------------- registration

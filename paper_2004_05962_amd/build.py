@@ -22,7 +22,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libbsi.so")
 OBJDIR = os.path.join(ROOT, "_build", "obj")
 
-SOURCES = ["lut.hip", "forward.hip", "lerp.hip", "adjoint.hip", "warp.hip", "fused.hip", "batch.hip", "abi.cpp"]
+SOURCES = ["lut.hip", "forward.hip", "lerp.hip", "adjoint.hip", "warp.hip", "fused.hip", "general.hip", "batch.hip", "abi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

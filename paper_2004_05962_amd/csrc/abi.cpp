@@ -243,6 +243,67 @@ int32_t bsi_adjoint_reduce(const void* workspace, size_t workspace_bytes, const 
   return e == hipSuccess ? BSI_OK : hip_fail(e, "launching the adjoint reduce kernel");
 }
 
+int32_t bsi_general_grid_dims(const int32_t dims[3], const float spacing[3], const float origin[3],
+                              int32_t out_g[3]) {
+  clear_error();
+  if (!out_g) return null_arg("out_g");
+  GenGeom q;
+  VolGeom g;
+  int32_t rc = make_gen_geom(dims, spacing, origin, &q, &g);
+  if (rc) return rc;
+  out_g[0] = g.gx;
+  out_g[1] = g.gy;
+  out_g[2] = g.gz;
+  return BSI_OK;
+}
+
+int32_t bsi_forward_general(const float* grid, const int32_t dims[3], const float spacing[3],
+                            const float origin[3], float* field, hipStream_t stream) {
+  clear_error();
+  GenGeom q;
+  VolGeom g;
+  int32_t rc = make_gen_geom(dims, spacing, origin, &q, &g);
+  if (rc) return rc;
+  if (!grid) return null_arg("grid");
+  if (!field) return null_arg("field");
+  if ((rc = device_only())) return rc;
+  hipError_t e = launch_forward_general(grid, field, g, q, stream);
+  return e == hipSuccess ? BSI_OK : hip_fail(e, "launching the general forward kernel");
+}
+
+int32_t bsi_adjoint_general_workspace_size(const int32_t dims[3], const float spacing[3],
+                                           const float origin[3], size_t* bytes) {
+  clear_error();
+  if (!bytes) return null_arg("bytes");
+  GenGeom q;
+  VolGeom g;
+  int32_t rc = make_gen_geom(dims, spacing, origin, &q, &g);
+  if (rc) return rc;
+  *bytes = general_workspace_bytes(q);
+  return BSI_OK;
+}
+
+int32_t bsi_adjoint_general(const float* dfield, const int32_t dims[3], const float spacing[3],
+                            const float origin[3], float* grid_grad, void* workspace, size_t workspace_bytes,
+                            hipStream_t stream) {
+  clear_error();
+  GenGeom q;
+  VolGeom g;
+  int32_t rc = make_gen_geom(dims, spacing, origin, &q, &g);
+  if (rc) return rc;
+  if (!dfield) return null_arg("dfield");
+  if (!grid_grad) return null_arg("grid_grad");
+  if (!workspace) return null_arg("workspace");
+  const size_t need = general_workspace_bytes(q);
+  if (workspace_bytes < need) {
+    set_error("workspace too small: need " + std::to_string(need) + " bytes");
+    return BSI_ERR_INVALID_ARG;
+  }
+  if ((rc = device_only())) return rc;
+  hipError_t e = launch_adjoint_general(dfield, grid_grad, q, workspace, stream);
+  return e == hipSuccess ? BSI_OK : hip_fail(e, "launching the general adjoint kernels");
+}
+
 int32_t bsi_warp(const float* field, const float* image, const int32_t dims[3], float* out,
                  hipStream_t stream) {
   clear_error();

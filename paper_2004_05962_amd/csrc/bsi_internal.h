@@ -62,6 +62,22 @@ hipError_t launch_sum(const float* partials, long n, float* out, hipStream_t s);
 size_t fused_workspace_bytes(const AdjGeom& a);
 hipError_t launch_ssd_fused(const float* grid, const float* moving, const float* fixed, float* grad, float* loss,
                             const AdjGeom& a, const float* lut, void* workspace, hipStream_t s);
+// Real spacing s and origin o per axis (general.hip): control point a at voxel
+// o + (a - 1) s, n voxels, g control points.
+struct GenAxis {
+  double s, o;
+  int n, g;
+};
+struct GenGeom {
+  GenAxis x, y, z;
+};
+int32_t make_gen_geom(const int32_t dims[3], const float spacing[3], const float origin[3], GenGeom* q,
+                      VolGeom* g);
+hipError_t launch_forward_general(const float* grid, float* field, const VolGeom& g, const GenGeom& q,
+                                  hipStream_t s);
+size_t general_workspace_bytes(const GenGeom& q);
+hipError_t launch_adjoint_general(const float* dfield, float* grad, const GenGeom& q, void* workspace,
+                                  hipStream_t s);
 hipError_t launch_descent(float* grid, const float* grad, float eta, int64_t count, hipStream_t s);
 
 }  // namespace bsi

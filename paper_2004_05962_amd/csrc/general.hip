@@ -1,0 +1,270 @@
+// BSI for a control grid with real spacing and an origin offset: the paper's
+// method needs the grid aligned to the voxels with integer spacing (Sec. 3.4),
+// the limitation its conclusion names (Sec. 8).  Per axis:
+//   control point a sits at voxel o + (a - 1) s      (s >= 1, -s < o <= 0),
+//   voxel x: t = (x - o) / s, window i = floor(t) .. i + 3, weights B(t - i),
+//   g = floor((n - 1 - o) / s) + 4 points.
+// t is formed in FP64 from the FP32 values of s and o, the same two IEEE
+// operations on the host and the device, so every window decision agrees; the
+// weights are evaluated in FP64 and rounded to FP32.
+//
+// Forward: the aligned kernel's structure (forward.hip) with weights computed
+// per coordinate instead of looked up per offset: x weights once per lane, y
+// weights once per wave, z weights once per plane, control planes staged per
+// workgroup in LDS and contracted once per row.  Tiles have varying voxel
+// counts, so the window of 4 contracted planes advances whenever floor(t_z)
+// does (at most once per voxel plane since s >= 1).
+//
+// Adjoint: three separable gathers in a fixed order, one output per thread:
+//   A[z][y][cx]  = sum_x  Bx(x; cx)  dfield[z][y][x]       x ascending
+//   Bm[z][cy][cx] = sum_y By(y; cy)  A[z][y][cx]           y ascending
+//   grad[cz][cy][cx] = sum_z Bz(z; cz) Bm[z][cy][cx]        z ascending
+// where B(x; c) = B_{c - i(x)}(u(x)) for the voxels whose window holds c.  The
+// per-axis tables i(x), B(u(x)) are computed once per call into the workspace.
+#include <cmath>
+
+#include "bsi_internal.h"
+
+namespace bsi {
+
+__host__ __device__ inline double gen_t(const GenAxis& a, int v) { return ((double)v - a.o) / a.s; }
+__host__ __device__ inline int gen_tile(const GenAxis& a, int v) { return (int)floor(gen_t(a, v)); }
+
+namespace {
+
+__device__ __forceinline__ int gen_weights(const GenAxis& a, int v, float (&w)[4]) {
+  const double t = gen_t(a, v);
+  const double fi = floor(t);
+  const double u = t - fi, r = 1.0 - u, u2 = u * u, u3 = u2 * u;
+  w[0] = (float)(r * r * r / 6.0);
+  w[1] = (float)((3.0 * u3 - 6.0 * u2 + 4.0) / 6.0);
+  w[2] = (float)((-3.0 * u3 + 3.0 * u2 + 3.0 * u + 1.0) / 6.0);
+  w[3] = (float)(u3 / 6.0);
+  return (int)fi;
+}
+
+__global__ __launch_bounds__(kFwdThreads) void gen_fwd_kernel(const float* __restrict__ grid,
+                                                               float* __restrict__ field, VolGeom g, GenGeom q,
+                                                               int nbx, int nby, int zchunk) {
+  __shared__ FwdSmem<3> sm;
+  int id = xcd_remap(blockIdx.x, gridDim.x);
+  const int bxi = id % nbx;
+  id /= nbx;
+  const int byi = id % nby;
+  const int bzi = id / nby;
+  const int tid = threadIdx.x;
+  const int x0 = bxi * kWave, y0 = byi * kFwdRows;
+  const int z0 = bzi * zchunk, z1 = min(g.nz, z0 + zchunk);
+  const int lane = tid & (kWave - 1);
+  const int wave = uniform(tid / kWave);
+  // s >= 1: 64 voxels span at most 63 tile steps, so the window fits the
+  // staging layout (at most kFwdMaxCx x kFwdMaxCy points)
+  const int cx0 = gen_tile(q.x, x0);
+  const int ncx = gen_tile(q.x, min(x0 + kWave, g.nx) - 1) - cx0 + 4;
+  const int cy0 = gen_tile(q.y, y0);
+  const int ncy = gen_tile(q.y, min(y0 + kFwdRows, g.ny) - 1) - cy0 + 4;
+  const FwdStage<3> map = fwd_stage_map<3>(g, cx0, ncx, cy0, ncy, tid);
+
+  const int x = x0 + lane, y = y0 + wave;
+  const bool active = x < g.nx && y < g.ny;
+  const int xc = min(x, g.nx - 1), yc = min(y, g.ny - 1);
+  float bx[4], wy[4];
+  const int tx = gen_weights(q.x, xc, bx);
+  const int ty = gen_weights(q.y, yc, wy);
+  const int base = (ty - cy0) * fwd_pitch<3>() + (tx - cx0) * 3;
+
+  int tz = gen_tile(q.z, z0);
+  float r[fwd_loads<3>()];
+  FwdVal<3> qv[4];
+#pragma unroll
+  for (int n = 0; n < 4; ++n) qv[n].v[0] = qv[n].v[1] = qv[n].v[2] = 0.f;
+#pragma unroll 1
+  for (int j = 0; j < 4; ++j) {
+    __syncthreads();
+    fwd_fetch<3>(grid, g, map, tz + j, r);
+    fwd_stage<3>(sm.ring[j & 1], tid, r);
+    __syncthreads();
+    const FwdVal<3> v = fwd_contract<3>(sm.ring[j & 1], base, bx[0], bx[1], bx[2], bx[3], wy);
+#pragma unroll
+    for (int n = 0; n < 4; ++n) qv[n] = n == j ? v : qv[n];
+  }
+  const size_t zstride = (size_t)g.ny * g.nx * 3;
+  float* out = field + (((size_t)z0 * g.ny + yc) * g.nx + xc) * 3;
+  for (int z = z0; z < z1; ++z, out += zstride) {
+    float wz[4];
+    const int t = gen_weights(q.z, z, wz);  // uniform
+    while (tz < t) {
+      // plane tz + 4 <= t + 3 <= floor((nz - 1 - o) / s) + 3 = gz - 1
+      __syncthreads();
+      fwd_fetch<3>(grid, g, map, tz + 4, r);
+      fwd_stage<3>(sm.ring[0], tid, r);
+      __syncthreads();
+      const FwdVal<3> v = fwd_contract<3>(sm.ring[0], base, bx[0], bx[1], bx[2], bx[3], wy);
+      qv[0] = qv[1];
+      qv[1] = qv[2];
+      qv[2] = qv[3];
+      qv[3] = v;
+      ++tz;
+    }
+    float o3[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      o3[c] = fmaf(wz[3], qv[3].v[c], fmaf(wz[2], qv[2].v[c], fmaf(wz[1], qv[1].v[c], wz[0] * qv[0].v[c])));
+    if (active) fwd_store<3>(out, o3);
+  }
+}
+
+// Per-axis tables: tile[v] = i(v), w[v][0..3] = B(u(v)), for v < n.
+__global__ __launch_bounds__(256) void gen_table_kernel(GenAxis a, int* __restrict__ tile,
+                                                         float* __restrict__ w) {
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  if (v >= a.n) return;
+  float b[4];
+  tile[v] = gen_weights(a, v, b);
+#pragma unroll
+  for (int l = 0; l < 4; ++l) w[4 * v + l] = b[l];
+}
+
+// One separable gather along an axis.  The input is viewed as [outer][n][inner]
+// F3 values (n along the axis), the output as [outer][g][inner]; output
+// (o, c, k) sums the inputs (o, v, k) whose window holds c, v ascending.
+__global__ __launch_bounds__(256) void gen_gather_kernel(const float* __restrict__ in, float* __restrict__ out,
+                                                          GenAxis a, const int* __restrict__ tile,
+                                                          const float* __restrict__ w, long outer, int inner) {
+  const long id = (long)blockIdx.x * 256 + threadIdx.x;
+  const long total = outer * a.g * (long)inner;
+  if (id >= total) return;
+  const int k = (int)(id % inner);
+  const long rest = id / inner;
+  const int c = (int)(rest % a.g);
+  const long o = rest / a.g;
+  // first voxel whose window can hold c: t >= c - 3, i.e. v >= (c - 3) s + o;
+  // start one below the estimate and skip voxels whose window ends before c
+  int v = (int)floor((double)(c - 3) * a.s + a.o) - 1;
+  if (v < 0) v = 0;
+  float sx = 0.f, sy = 0.f, sz = 0.f;
+  const float* src = in + ((size_t)o * a.n * inner + k) * 3;
+  for (; v < a.n; ++v) {
+    const int i = tile[v];
+    if (i > c) break;        // windows only move right
+    if (i < c - 3) continue;
+    const float b = w[4 * v + (c - i)];
+    const float* p = src + (size_t)v * inner * 3;
+    sx = fmaf(b, p[0], sx);
+    sy = fmaf(b, p[1], sy);
+    sz = fmaf(b, p[2], sz);
+  }
+  float* dst = out + (((size_t)o * a.g + c) * inner + k) * 3;
+  dst[0] = sx;
+  dst[1] = sy;
+  dst[2] = sz;
+}
+
+constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+struct GenWork {
+  int* tile[3];
+  float* w[3];
+  float* A;   // [nz][ny][gx][3]
+  float* Bm;  // [nz][gy][gx][3]
+};
+
+size_t gen_layout(const GenGeom& q, void* base, GenWork* wk) {
+  char* p = static_cast<char*>(base);
+  size_t off = 0;
+  const GenAxis* ax[3] = {&q.x, &q.y, &q.z};
+  for (int i = 0; i < 3; ++i) {
+    if (wk) wk->tile[i] = reinterpret_cast<int*>(p + off);
+    off += align256((size_t)ax[i]->n * sizeof(int));
+    if (wk) wk->w[i] = reinterpret_cast<float*>(p + off);
+    off += align256((size_t)ax[i]->n * 4 * sizeof(float));
+  }
+  if (wk) wk->A = reinterpret_cast<float*>(p + off);
+  off += align256((size_t)q.z.n * q.y.n * q.x.g * 3 * sizeof(float));
+  if (wk) wk->Bm = reinterpret_cast<float*>(p + off);
+  off += align256((size_t)q.z.n * q.y.g * q.x.g * 3 * sizeof(float));
+  return off;
+}
+
+unsigned blocks_for(long n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+int32_t make_gen_geom(const int32_t dims[3], const float spacing[3], const float origin[3], GenGeom* q, VolGeom* g) {
+  if (!dims || !spacing || !origin) {
+    set_error("dims, spacing and origin must be non-null");
+    return BSI_ERR_INVALID_ARG;
+  }
+  GenAxis* ax[3] = {&q->x, &q->y, &q->z};
+  for (int i = 0; i < 3; ++i) {
+    const double s = spacing[i], o = origin[i];
+    if (dims[i] < 1 || !std::isfinite(s) || !std::isfinite(o) || s < 1.0 || !(o <= 0.0 && o > -s)) {
+      set_error("need dims >= 1, spacing >= 1 and -spacing < origin <= 0 on every axis");
+      return BSI_ERR_INVALID_ARG;
+    }
+    if (s > BSI_MAX_SPACING || dims[i] > BSI_MAX_DIM) {
+      set_error("spacing above BSI_MAX_SPACING or an axis above BSI_MAX_DIM");
+      return BSI_ERR_UNSUPPORTED;
+    }
+    ax[i]->s = s;
+    ax[i]->o = o;
+    ax[i]->n = dims[i];
+    ax[i]->g = gen_tile(*ax[i], dims[i] - 1) + 4;
+  }
+  const double rows = (double)dims[1] * dims[2];
+  if (rows > 2.0e9 || rows * dims[0] * 3 > 9.0e18 / 16) {
+    set_error("volume too large");
+    return BSI_ERR_UNSUPPORTED;
+  }
+  g->nx = dims[0];
+  g->ny = dims[1];
+  g->nz = dims[2];
+  g->dx = g->dy = g->dz = 1;  // unused: the general kernels take tiles from q
+  g->gx = q->x.g;
+  g->gy = q->y.g;
+  g->gz = q->z.g;
+  return BSI_OK;
+}
+
+hipError_t launch_forward_general(const float* grid, float* field, const VolGeom& g, const GenGeom& q,
+                                  hipStream_t s) {
+  const int nbx = (g.nx + kWave - 1) / kWave, nby = (g.ny + kFwdRows - 1) / kFwdRows;
+  const long base = (long)nbx * nby;
+  int chunks = (int)((kFwdTargetBlocks + base - 1) / base);
+  chunks = std::max(1, std::min(chunks, g.nz));
+  const int zchunk = (g.nz + chunks - 1) / chunks;
+  const int nbz = (g.nz + zchunk - 1) / zchunk;
+  hipLaunchKernelGGL(gen_fwd_kernel, dim3((unsigned)(base * nbz)), dim3(kFwdThreads), 0, s, grid, field, g, q,
+                     nbx, nby, zchunk);
+  return hipGetLastError();
+}
+
+size_t general_workspace_bytes(const GenGeom& q) { return gen_layout(q, nullptr, nullptr); }
+
+hipError_t launch_adjoint_general(const float* dfield, float* grad, const GenGeom& q, void* workspace,
+                                  hipStream_t s) {
+  GenWork wk;
+  gen_layout(q, workspace, &wk);
+  const GenAxis* ax[3] = {&q.x, &q.y, &q.z};
+  for (int i = 0; i < 3; ++i) {
+    hipLaunchKernelGGL(gen_table_kernel, dim3(blocks_for(ax[i]->n)), dim3(256), 0, s, *ax[i], wk.tile[i], wk.w[i]);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  // x: [nz*ny][nx][1] -> A [nz*ny][gx][1]
+  const long rows = (long)q.z.n * q.y.n;
+  hipLaunchKernelGGL(gen_gather_kernel, dim3(blocks_for(rows * q.x.g)), dim3(256), 0, s, dfield, wk.A, q.x,
+                     wk.tile[0], wk.w[0], rows, 1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // y: [nz][ny][gx] -> Bm [nz][gy][gx]
+  hipLaunchKernelGGL(gen_gather_kernel, dim3(blocks_for((long)q.z.n * q.y.g * q.x.g)), dim3(256), 0, s, wk.A,
+                     wk.Bm, q.y, wk.tile[1], wk.w[1], (long)q.z.n, q.x.g);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // z: [1][nz][gy*gx] -> grad [gz][gy*gx]
+  hipLaunchKernelGGL(gen_gather_kernel, dim3(blocks_for((long)q.z.g * q.y.g * q.x.g)), dim3(256), 0, s, wk.Bm,
+                     grad, q.z, wk.tile[2], wk.w[2], 1L, q.y.g * q.x.g);
+  return hipGetLastError();
+}
+
+}  // namespace bsi

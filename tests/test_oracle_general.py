@@ -66,3 +66,13 @@ def test_grid_dims_formula_and_checks():
         general.grid_dims((10, 1, 1), (2.0, 1, 1), (0.5, 0, 0))
     with pytest.raises(ValueError):
         general.grid_dims((10, 1, 1), (0.5, 1, 1), (0, 0, 0))
+
+
+def test_points_match_full_forward():
+    dims, spacing, origin = (15, 11, 9), (2.6, 1.3, 3.9), (-2.0, -0.3, 0.0)
+    g = _grid(dims, spacing, origin, seed=11)
+    f = general.forward(g, dims, spacing, origin)
+    rng = np.random.default_rng(1)
+    pts = np.stack([rng.integers(0, n, 50) for n in dims], axis=1)
+    np.testing.assert_allclose(general.forward_points(g, dims, spacing, origin, pts),
+                               f[pts[:, 2], pts[:, 1], pts[:, 0]], rtol=0, atol=1e-13)
