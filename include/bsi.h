@@ -248,10 +248,11 @@ int32_t bsi_batch_bind(bsi_batch* plan, const float* const* grids, float* const*
                        const float* const* dfields, float* const* grid_grads);
 
 /* Time the candidate schedules (persistent grid size, work order) on `stream`
-   with the bound buffers and keep the fastest.  The choice is stored in the
-   JSON file named by the environment variable BSI_TUNE_CACHE (if set) and read
-   back by later plans with the same geometry.  BSI_FORCE_CONFIG=<index> skips
-   timing.  Synchronises `stream`.  Schedules never change result bits. */
+   with the bound buffers (the outputs are written while timing) and keep the
+   fastest.  Drops a captured graph.  The choice is stored in the JSON file
+   named by the environment variable BSI_TUNE_CACHE (if set) and read back by
+   later plans with the same geometry.  BSI_FORCE_CONFIG=<index> skips timing.
+   Synchronises `stream`.  Schedules never change result bits. */
 int32_t bsi_batch_tune(bsi_batch* plan, hipStream_t stream);
 
 /* Index of the schedule the plan uses, and the number of candidates. */

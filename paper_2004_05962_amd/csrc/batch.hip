@@ -10,7 +10,9 @@
 // change the arithmetic.
 //
 // Graph shape: the forward (grid -> field) and the adjoint (dfield -> grad) are
-// independent, so they run as two parallel branches (fork/join with events).
+// independent, so they run as parallel branches (fork/join with events); the
+// adjoint's pass-1 launches, one per x-spacing class, are spread over several
+// streams as well, so that their tails overlap, and join before pass 2.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,6 +44,11 @@ enum Pass { kFwd = 0, kAdj1 = 1, kAdj2 = 2 };
 constexpr int kNumClasses = kAdjMaxDX + 1;  // class dx for dx <= kAdjMaxDX, class 0 otherwise
 inline int dx_class(int dx) { return dx <= kAdjMaxDX ? dx : 0; }
 constexpr int kPtThreads = 256;
+#ifndef BSI_BATCH_FWD_TARGET
+#define BSI_BATCH_FWD_TARGET 2048
+#endif
+constexpr long kBatchFwdTarget = BSI_BATCH_FWD_TARGET;  // forward items per volume (z split)
+constexpr int kClassStreams = 3;  // pass-1 class launches run on the caller's stream and these
 
 struct Schedule {
   int fwd_per_cu;  // persistent workgroups per CU (0 = one workgroup per item)
@@ -50,12 +57,15 @@ struct Schedule {
   int chunked;     // 0: item = wg + k * G;  1: contiguous slices per workgroup
 };
 
-// Candidate schedules; index 0 is the non-persistent reference.
+// Candidate schedules; index 0 is the non-persistent reference.  (Persistent
+// grids of 1-2 workgroups per CU for pass 1, and contiguous slices, measured
+// 8-50% slower once the pass-1 classes run concurrently, and are not offered.)
 static const Schedule kSchedules[] = {
-    {0, 0, 0, 0}, {4, 2, 8, 0}, {4, 2, 8, 1}, {2, 1, 4, 0}, {2, 1, 4, 1}, {8, 2, 8, 1},
+    {0, 0, 0, 0},
+    {4, 2, 8, 0},
 };
 constexpr int kNumSchedules = sizeof(kSchedules) / sizeof(kSchedules[0]);
-constexpr int kDefaultSchedule = 2;
+constexpr int kDefaultSchedule = 0;
 
 __device__ __forceinline__ int find_volume(const VolDesc* __restrict__ v, int count, int64_t item, int pass) {
   int lo = 0, hi = count - 1;  // last volume whose first item <= item
@@ -171,6 +181,8 @@ struct bsi_batch {
   std::string key;
   hipStream_t side = nullptr;  // second branch (forward) of run / capture
   hipEvent_t fork = nullptr, join = nullptr;
+  hipStream_t cls_side[kClassStreams] = {};  // further branches of adjoint pass 1
+  hipEvent_t cls_join[kClassStreams] = {};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -207,33 +219,7 @@ hipError_t launch_pass(bsi_batch* p, int pass, hipStream_t s) {
     hipLaunchKernelGGL(batch_fwd_kernel, dim3((unsigned)grid), dim3(kFwdThreads), 0, s, p->d_desc,
                        p->count, total, chunked, p->lut);
   } else if (pass == kAdj1) {
-    for (int c = 0; c < kNumClasses; ++c) {
-      const int n = p->cls_first[c + 1] - p->cls_first[c];
-      const int64_t ct = p->cls_total[c];
-      if (n == 0 || ct == 0) continue;
-      const int64_t cg = per_cu == 0 ? ct : std::min<int64_t>(ct, (int64_t)per_cu * p->cus);
-      const dim3 gd((unsigned)cg), bd(kAdjThreads);
-      const VolDesc* v = p->d_cls + p->cls_first[c];
-      static_assert(kAdjMaxDX == 12, "one case per specialised spacing");
-      switch (c) {
-        case 1: hipLaunchKernelGGL(batch_adj1_kernel<1>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
-        case 2: hipLaunchKernelGGL(batch_adj1_kernel<2>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
-        case 3: hipLaunchKernelGGL(batch_adj1_kernel<3>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
-        case 4: hipLaunchKernelGGL(batch_adj1_kernel<4>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
-        case 5: hipLaunchKernelGGL(batch_adj1_kernel<5>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
-        case 6: hipLaunchKernelGGL(batch_adj1_kernel<6>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
-        case 7: hipLaunchKernelGGL(batch_adj1_kernel<7>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
-        case 8: hipLaunchKernelGGL(batch_adj1_kernel<8>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
-        case 9: hipLaunchKernelGGL(batch_adj1_kernel<9>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
-        case 10: hipLaunchKernelGGL(batch_adj1_kernel<10>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
-        case 11: hipLaunchKernelGGL(batch_adj1_kernel<11>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
-        case 12: hipLaunchKernelGGL(batch_adj1_kernel<12>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
-        default: hipLaunchKernelGGL(batch_adj1_kernel<0>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
-      }
-      hipError_t e = hipGetLastError();
-      if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    return hipErrorInvalidValue;  // pass 1 is launched per class (launch_adj1_class)
   } else {
     hipLaunchKernelGGL(batch_adj2_kernel, dim3((unsigned)grid), dim3(kPtThreads), 0, s, p->d_desc, p->count,
                        total, chunked);
@@ -241,23 +227,99 @@ hipError_t launch_pass(bsi_batch* p, int pass, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Adjoint pass 1 over the volumes of x-spacing class c, on stream s.
+hipError_t launch_adj1_class(bsi_batch* p, int c, hipStream_t s) {
+  const Schedule& sc = kSchedules[p->schedule];
+  const int n = p->cls_first[c + 1] - p->cls_first[c];
+  const int64_t ct = p->cls_total[c];
+  if (n == 0 || ct == 0) return hipSuccess;
+  const int per_cu = sc.adj_per_cu;
+  const int chunked = per_cu == 0 ? 0 : sc.chunked;
+  const int64_t cg = per_cu == 0 ? ct : std::min<int64_t>(ct, (int64_t)per_cu * p->cus);
+  const dim3 gd((unsigned)cg), bd(kAdjThreads);
+  const VolDesc* v = p->d_cls + p->cls_first[c];
+  static_assert(kAdjMaxDX == 12, "one case per specialised spacing");
+  switch (c) {
+    case 1: hipLaunchKernelGGL(batch_adj1_kernel<1>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+    case 2: hipLaunchKernelGGL(batch_adj1_kernel<2>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+    case 3: hipLaunchKernelGGL(batch_adj1_kernel<3>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+    case 4: hipLaunchKernelGGL(batch_adj1_kernel<4>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+    case 5: hipLaunchKernelGGL(batch_adj1_kernel<5>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+    case 6: hipLaunchKernelGGL(batch_adj1_kernel<6>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+    case 7: hipLaunchKernelGGL(batch_adj1_kernel<7>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+    case 8: hipLaunchKernelGGL(batch_adj1_kernel<8>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+    case 9: hipLaunchKernelGGL(batch_adj1_kernel<9>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+    case 10: hipLaunchKernelGGL(batch_adj1_kernel<10>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+    case 11: hipLaunchKernelGGL(batch_adj1_kernel<11>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+    case 12: hipLaunchKernelGGL(batch_adj1_kernel<12>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+    default: hipLaunchKernelGGL(batch_adj1_kernel<0>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+  }
+  return hipGetLastError();
+}
+
+// Adjoint pass 1 (every class) then pass 2, on `s`.  Classes go round-robin
+// over `s` and the plan's class streams, largest first; each class stream
+// waits for p->fork, which the caller has recorded on `s`, and is joined back
+// into `s` before pass 2.
+int32_t enqueue_adjoint(bsi_batch* p, hipStream_t s) {
+  hipError_t e;
+  int order[kNumClasses];
+  int used = 0;
+  for (int c = 0; c < kNumClasses; ++c)
+    if (p->cls_total[c] > 0) order[used++] = c;
+  std::stable_sort(order, order + used, [p](int a, int b) { return p->cls_total[a] > p->cls_total[b]; });
+  const int branches = std::min(used, kClassStreams + 1);
+  for (int j = 0; j + 1 < branches; ++j)
+    if ((e = hipStreamWaitEvent(p->cls_side[j], p->fork, 0)) != hipSuccess) return hip_fail(e, "forking pass 1");
+  for (int k = 0; k < used; ++k) {
+    const int b = k % branches;
+    hipStream_t st = b == 0 ? s : p->cls_side[b - 1];
+    if ((e = launch_adj1_class(p, order[k], st)) != hipSuccess) return hip_fail(e, "launching batched adjoint pass 1");
+  }
+  for (int j = 0; j + 1 < branches; ++j) {
+    if ((e = hipEventRecord(p->cls_join[j], p->cls_side[j])) != hipSuccess) return hip_fail(e, "recording a pass-1 join");
+    if ((e = hipStreamWaitEvent(s, p->cls_join[j], 0)) != hipSuccess) return hip_fail(e, "joining pass 1");
+  }
+  if ((e = launch_pass(p, kAdj2, s)) != hipSuccess) return hip_fail(e, "launching batched adjoint pass 2");
+  return BSI_OK;
+}
+
 // Forward on the side stream, adjoint on `s`, joined back into `s`.
 int32_t enqueue(bsi_batch* p, hipStream_t s) {
   hipError_t e;
+  if (p->has_adj && (e = hipEventRecord(p->fork, s)) != hipSuccess) return hip_fail(e, "recording the fork event");
   if (p->has_fwd && p->has_adj) {
-    if ((e = hipEventRecord(p->fork, s)) != hipSuccess) return hip_fail(e, "recording the fork event");
     if ((e = hipStreamWaitEvent(p->side, p->fork, 0)) != hipSuccess) return hip_fail(e, "forking");
     if ((e = launch_pass(p, kFwd, p->side)) != hipSuccess) return hip_fail(e, "launching the batched forward");
-    if ((e = launch_pass(p, kAdj1, s)) != hipSuccess) return hip_fail(e, "launching batched adjoint pass 1");
-    if ((e = launch_pass(p, kAdj2, s)) != hipSuccess) return hip_fail(e, "launching batched adjoint pass 2");
+    const int32_t rc = enqueue_adjoint(p, s);
+    if (rc) return rc;
     if ((e = hipEventRecord(p->join, p->side)) != hipSuccess) return hip_fail(e, "recording the join event");
     if ((e = hipStreamWaitEvent(s, p->join, 0)) != hipSuccess) return hip_fail(e, "joining");
     return BSI_OK;
   }
   if (p->has_fwd && (e = launch_pass(p, kFwd, s)) != hipSuccess) return hip_fail(e, "launching the batched forward");
-  if (p->has_adj) {
-    if ((e = launch_pass(p, kAdj1, s)) != hipSuccess) return hip_fail(e, "launching batched adjoint pass 1");
-    if ((e = launch_pass(p, kAdj2, s)) != hipSuccess) return hip_fail(e, "launching batched adjoint pass 2");
+  if (p->has_adj) return enqueue_adjoint(p, s);
+  return BSI_OK;
+}
+
+// Capture enqueue() on `stream` into the plan's graph and instantiate it.
+int32_t build_graph(bsi_batch* p, hipStream_t stream) {
+  drop_graph(p);
+  hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "beginning stream capture");
+  int32_t rc = enqueue(p, stream);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(stream, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e, "ending stream capture");
+  p->graph = g;
+  e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    drop_graph(p);
+    return hip_fail(e, "instantiating the graph");
   }
   return BSI_OK;
 }
@@ -344,17 +406,23 @@ int32_t bsi_batch_create(int32_t count, const int32_t* dims3xN, const int32_t* s
   std::vector<size_t> off((size_t)count);
   size_t part_floats = 0;
   int64_t tot[3] = {0, 0, 0};
+  std::vector<VolGeom> geoms((size_t)count);
   for (int i = 0; i < count; ++i) {
-    VolGeom g;
-    int32_t rc = make_geom(dims3xN + 3 * i, spacing3xN + 3 * i, &g);
+    int32_t rc = make_geom(dims3xN + 3 * i, spacing3xN + 3 * i, &geoms[i]);
     if (rc) {
       set_error("volume " + std::to_string(i) + ": " + bsi_last_error());
       return rc;
     }
+  }
+  for (int i = 0; i < count; ++i) {
+    const VolGeom& g = geoms[i];
     VolDesc& d = host[i];
     std::memset(&d, 0, sizeof(d));
     d.a = make_adj_geom(g);
-    d.f = make_fwd_launch(g);
+    // Each volume's forward is split in z to about kBatchFwdTarget items:
+    // fewer than a standalone launch needs (the batch fills the GPU), more than
+    // one item per column (short items balance better across the batch).
+    d.f = make_fwd_launch(g, kBatchFwdTarget);
     off[i] = part_floats;
     part_floats += adj_workspace_bytes(d.a) / sizeof(float);
     d.first[kFwd] = tot[kFwd];
@@ -414,6 +482,12 @@ int32_t bsi_batch_create(int32_t count, const int32_t* dims3xN, const int32_t* s
     bsi_batch_destroy(p);
     return hip_fail(e, "creating the plan's stream and events");
   }
+  for (int j = 0; j < kClassStreams; ++j)
+    if ((e = hipStreamCreateWithFlags(&p->cls_side[j], hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&p->cls_join[j], hipEventDisableTiming)) != hipSuccess) {
+      bsi_batch_destroy(p);
+      return hip_fail(e, "creating the plan's pass-1 streams and events");
+    }
   p->key = plan_key(p);
   if (const char* force = std::getenv("BSI_FORCE_CONFIG")) {
     const int v = std::atoi(force);
@@ -535,29 +609,36 @@ int32_t bsi_batch_tune(bsi_batch* p, hipStream_t stream) {
     return hip_fail(e, "creating a timing event");
   }
   const int keep = p->schedule;
+  // Two sweeps over the schedules (the first also warms clocks and caches);
+  // each schedule keeps the better of its two medians of 5 timed runs.
+  float sched_ms[kNumSchedules];
+  for (int c = 0; c < kNumSchedules; ++c) sched_ms[c] = 1e30f;
+  for (int sweep = 0; sweep < 2 && rc == BSI_OK; ++sweep)
+    for (int c = 0; c < kNumSchedules && rc == BSI_OK; ++c) {
+      p->schedule = c;
+      if ((rc = enqueue(p, stream))) break;  // warm-up
+      float times[5];
+      for (int r = 0; r < 5 && rc == BSI_OK; ++r) {
+        if ((e = hipEventRecord(t0, stream)) != hipSuccess) {
+          rc = hip_fail(e, "recording a timing event");
+          break;
+        }
+        if ((rc = enqueue(p, stream))) break;
+        if ((e = hipEventRecord(t1, stream)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess ||
+            (e = hipEventElapsedTime(&times[r], t0, t1)) != hipSuccess)
+          rc = hip_fail(e, "timing a schedule");
+      }
+      if (rc) break;
+      std::sort(times, times + 5);
+      sched_ms[c] = std::min(sched_ms[c], times[2]);
+    }
   int best = keep;
   float best_ms = 1e30f;
-  for (int c = 0; c < kNumSchedules && rc == BSI_OK; ++c) {
-    p->schedule = c;
-    if ((rc = enqueue(p, stream))) break;  // warm-up
-    float times[5];
-    for (int r = 0; r < 5 && rc == BSI_OK; ++r) {
-      if ((e = hipEventRecord(t0, stream)) != hipSuccess) {
-        rc = hip_fail(e, "recording a timing event");
-        break;
-      }
-      if ((rc = enqueue(p, stream))) break;
-      if ((e = hipEventRecord(t1, stream)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess ||
-          (e = hipEventElapsedTime(&times[r], t0, t1)) != hipSuccess)
-        rc = hip_fail(e, "timing a schedule");
-    }
-    if (rc) break;
-    std::sort(times, times + 5);
-    if (times[2] < best_ms) {
-      best_ms = times[2];
+  for (int c = 0; c < kNumSchedules; ++c)
+    if (sched_ms[c] < best_ms) {
+      best_ms = sched_ms[c];
       best = c;
     }
-  }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   p->schedule = rc == BSI_OK ? best : keep;
@@ -575,24 +656,7 @@ int32_t bsi_batch_capture(bsi_batch* p, hipStream_t stream) {
   }
   int32_t rc = check_device(p);
   if (rc) return rc;
-  drop_graph(p);
-  hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) return hip_fail(e, "beginning stream capture");
-  rc = enqueue(p, stream);
-  hipGraph_t g = nullptr;
-  e = hipStreamEndCapture(stream, &g);
-  if (rc) {
-    if (g) (void)hipGraphDestroy(g);
-    return rc;
-  }
-  if (e != hipSuccess) return hip_fail(e, "ending stream capture");
-  p->graph = g;
-  e = hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0);
-  if (e != hipSuccess) {
-    drop_graph(p);
-    return hip_fail(e, "instantiating the graph");
-  }
-  return BSI_OK;
+  return build_graph(p, stream);
 }
 
 int32_t bsi_batch_launch(bsi_batch* p, hipStream_t stream) {
@@ -618,6 +682,10 @@ void bsi_batch_destroy(bsi_batch* p) {
   if (p->fork) (void)hipEventDestroy(p->fork);
   if (p->join) (void)hipEventDestroy(p->join);
   if (p->side) (void)hipStreamDestroy(p->side);
+  for (int j = 0; j < kClassStreams; ++j) {
+    if (p->cls_join[j]) (void)hipEventDestroy(p->cls_join[j]);
+    if (p->cls_side[j]) (void)hipStreamDestroy(p->cls_side[j]);
+  }
   if (p->d_desc) (void)hipFree(p->d_desc);
   if (p->d_cls) (void)hipFree(p->d_cls);
   if (p->d_part) (void)hipFree(p->d_part);

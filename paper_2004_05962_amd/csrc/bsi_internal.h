@@ -37,7 +37,7 @@ struct FwdLaunch {
 #define BSI_FWD_BLOCKS 2048
 #endif
 constexpr int kFwdTargetBlocks = BSI_FWD_BLOCKS; // z is split until this many workgroups
-FwdLaunch make_fwd_launch(const VolGeom& g);
+FwdLaunch make_fwd_launch(const VolGeom& g, long target = kFwdTargetBlocks);
 
 hipError_t launch_forward(const float* grid, float* field, const VolGeom& g, const float* lut,
                           hipStream_t s);

@@ -26,15 +26,17 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(const float* __restric
   fwd_block<C>(grid, field, g, lut, bx * kWave, by * kFwdRows, z0, z1, sm, threadIdx.x);
 }
 
-FwdLaunch make_fwd_launch(const VolGeom& g) {
+FwdLaunch make_fwd_launch(const VolGeom& g, long target) {
   FwdLaunch L;
   L.nbx = (g.nx + kWave - 1) / kWave;
   L.nby = (g.ny + kFwdRows - 1) / kFwdRows;
-  // Split z (at tile boundaries) until there are >= kFwdTargetBlocks
-  // workgroups: enough waves to keep the stores flowing.
+  // Split z (at tile boundaries) until there are >= target workgroups: enough
+  // waves to keep the stores flowing, and no more (each chunk restages the 3
+  // control planes before its first tile).  The split does not change the
+  // arithmetic of any voxel.
   const int tiles_z = (g.nz + g.dz - 1) / g.dz;
   const long base = (long)L.nbx * L.nby;
-  int chunks = (int)((kFwdTargetBlocks + base - 1) / base);
+  int chunks = (int)((target + base - 1) / base);
   if (chunks > tiles_z) chunks = tiles_z;
   if (chunks < 1) chunks = 1;
   const int tiles_per_chunk = (tiles_z + chunks - 1) / chunks;
