@@ -8,12 +8,13 @@
 // operations on the host and the device, so every window decision agrees; the
 // weights are evaluated in FP64 and rounded to FP32.
 //
-// Forward: the aligned kernel's structure (forward.hip) with weights computed
+// Forward: the aligned kernel's pipeline (forward.hip) with weights computed
 // per coordinate instead of looked up per offset: x weights once per lane, y
-// weights once per wave, z weights once per plane, control planes staged per
-// workgroup in LDS and contracted once per row.  Tiles have varying voxel
-// counts, so the window of 4 contracted planes advances whenever floor(t_z)
-// does (at most once per voxel plane since s >= 1).
+// weights once per wave, and the window start and z weights of every plane of
+// the workgroup's z range once, into an LDS table.  Tiles have varying voxel
+// counts; the window of 4 contracted planes advances whenever floor(t_z) does
+// (by one, since s >= 1), with the next plane loaded while the current tile is
+// written and one barrier per tile.
 //
 // Adjoint: three separable gathers in a fixed order, one output per thread:
 //   A[z][y][cx]  = sum_x  Bx(x; cx)  dfield[z][y][x]       x ascending
@@ -43,10 +44,18 @@ __device__ __forceinline__ int gen_weights(const GenAxis& a, int v, float (&w)[4
   return (int)fi;
 }
 
+constexpr int kGenMaxZ = 256;  // voxel planes per workgroup (z table in LDS)
+
+struct GenFwdSmem {
+  FwdSmem<3> f;
+  float zw[kGenMaxZ][4];  // z weights of the workgroup's planes
+  int zt[kGenMaxZ];       // their window start floor(t_z)
+};
+
 __global__ __launch_bounds__(kFwdThreads) void gen_fwd_kernel(const float* __restrict__ grid,
                                                                float* __restrict__ field, VolGeom g, GenGeom q,
                                                                int nbx, int nby, int zchunk) {
-  __shared__ FwdSmem<3> sm;
+  __shared__ GenFwdSmem sm;
   int id = xcd_remap(blockIdx.x, gridDim.x);
   const int bxi = id % nbx;
   id /= nbx;
@@ -54,7 +63,7 @@ __global__ __launch_bounds__(kFwdThreads) void gen_fwd_kernel(const float* __res
   const int bzi = id / nby;
   const int tid = threadIdx.x;
   const int x0 = bxi * kWave, y0 = byi * kFwdRows;
-  const int z0 = bzi * zchunk, z1 = min(g.nz, z0 + zchunk);
+  const int z0 = bzi * zchunk, z1 = min(g.nz, z0 + zchunk);  // z1 - z0 <= kGenMaxZ
   const int lane = tid & (kWave - 1);
   const int wave = uniform(tid / kWave);
   // s >= 1: 64 voxels span at most 63 tile steps, so the window fits the
@@ -64,6 +73,13 @@ __global__ __launch_bounds__(kFwdThreads) void gen_fwd_kernel(const float* __res
   const int cy0 = gen_tile(q.y, y0);
   const int ncy = gen_tile(q.y, min(y0 + kFwdRows, g.ny) - 1) - cy0 + 4;
   const FwdStage<3> map = fwd_stage_map<3>(g, cx0, ncx, cy0, ncy, tid);
+  for (int i = tid; i < z1 - z0; i += kFwdThreads) {
+    float w[4];
+    sm.zt[i] = gen_weights(q.z, z0 + i, w);
+#pragma unroll
+    for (int n = 0; n < 4; ++n) sm.zw[i][n] = w[n];
+  }
+  // (the warm-up's first barrier orders the table before any read)
 
   const int x = x0 + lane, y = y0 + wave;
   const bool active = x < g.nx && y < g.ny;
@@ -75,42 +91,54 @@ __global__ __launch_bounds__(kFwdThreads) void gen_fwd_kernel(const float* __res
 
   int tz = gen_tile(q.z, z0);
   float r[fwd_loads<3>()];
-  FwdVal<3> qv[4];
+  // Warm-up as in the aligned forward: planes tz, tz+1, tz+2 through slots
+  // 0, 1, 0 into q0..q2, then plane tz+3 staged into slot 1.
+  FwdVal<3> q0, q1, q2;
 #pragma unroll
-  for (int n = 0; n < 4; ++n) qv[n].v[0] = qv[n].v[1] = qv[n].v[2] = 0.f;
+  for (int c = 0; c < 3; ++c) q0.v[c] = q1.v[c] = q2.v[c] = 0.f;
 #pragma unroll 1
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < 3; ++j) {
     __syncthreads();
     fwd_fetch<3>(grid, g, map, tz + j, r);
-    fwd_stage<3>(sm.ring[j & 1], tid, r);
+    fwd_stage<3>(sm.f.ring[j & 1], tid, r);
     __syncthreads();
-    const FwdVal<3> v = fwd_contract<3>(sm.ring[j & 1], base, bx[0], bx[1], bx[2], bx[3], wy);
-#pragma unroll
-    for (int n = 0; n < 4; ++n) qv[n] = n == j ? v : qv[n];
+    const FwdVal<3> qn = fwd_contract<3>(sm.f.ring[j & 1], base, bx[0], bx[1], bx[2], bx[3], wy);
+    q0 = q1;
+    q1 = q2;
+    q2 = qn;
   }
+  __syncthreads();
+  fwd_fetch<3>(grid, g, map, tz + 3, r);
+  fwd_stage<3>(sm.f.ring[1], tid, r);
+  __syncthreads();
+  int slot3 = 1;
+
   const size_t zstride = (size_t)g.ny * g.nx * 3;
   float* out = field + (((size_t)z0 * g.ny + yc) * g.nx + xc) * 3;
-  for (int z = z0; z < z1; ++z, out += zstride) {
-    float wz[4];
-    const int t = gen_weights(q.z, z, wz);  // uniform
-    while (tz < t) {
-      // plane tz + 4 <= t + 3 <= floor((nz - 1 - o) / s) + 3 = gz - 1
-      __syncthreads();
-      fwd_fetch<3>(grid, g, map, tz + 4, r);
-      fwd_stage<3>(sm.ring[0], tid, r);
-      __syncthreads();
-      const FwdVal<3> v = fwd_contract<3>(sm.ring[0], base, bx[0], bx[1], bx[2], bx[3], wy);
-      qv[0] = qv[1];
-      qv[1] = qv[2];
-      qv[2] = qv[3];
-      qv[3] = v;
-      ++tz;
-    }
-    float o3[3];
+  int z = z0;
+  for (;;) {
+    const FwdVal<3> q3 = fwd_contract<3>(sm.f.ring[slot3], base, bx[0], bx[1], bx[2], bx[3], wy);
+    int zend = z;  // the planes of tile tz in this chunk (s >= 1: the next one is tz + 1)
+    while (zend < z1 && sm.zt[zend - z0] == tz) ++zend;
+    const bool more = zend < z1;
+    // its new plane tz + 4 = t_z(zend) + 3 <= gz - 1: in bounds
+    if (more) fwd_fetch<3>(grid, g, map, tz + 4, r);
+    for (; z < zend; ++z, out += zstride) {
+      const float* wz = sm.zw[z - z0];
+      float t[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-      o3[c] = fmaf(wz[3], qv[3].v[c], fmaf(wz[2], qv[2].v[c], fmaf(wz[1], qv[1].v[c], wz[0] * qv[0].v[c])));
-    if (active) fwd_store<3>(out, o3);
+      for (int c = 0; c < 3; ++c)
+        t[c] = fmaf(wz[3], q3.v[c], fmaf(wz[2], q2.v[c], fmaf(wz[1], q1.v[c], wz[0] * q0.v[c])));
+      if (active) fwd_store<3>(out, t);
+    }
+    if (!more) break;
+    fwd_stage<3>(sm.f.ring[slot3 ^ 1], tid, r);
+    __syncthreads();
+    slot3 ^= 1;
+    ++tz;
+    q0 = q1;
+    q1 = q2;
+    q2 = q3;
   }
 }
 
@@ -231,6 +259,7 @@ hipError_t launch_forward_general(const float* grid, float* field, const VolGeom
   const int nbx = (g.nx + kWave - 1) / kWave, nby = (g.ny + kFwdRows - 1) / kFwdRows;
   const long base = (long)nbx * nby;
   int chunks = (int)((kFwdTargetBlocks + base - 1) / base);
+  chunks = std::max(chunks, (g.nz + kGenMaxZ - 1) / kGenMaxZ);  // the z table holds kGenMaxZ planes
   chunks = std::max(1, std::min(chunks, g.nz));
   const int zchunk = (g.nz + chunks - 1) / chunks;
   const int nbz = (g.nz + zchunk - 1) / zchunk;
