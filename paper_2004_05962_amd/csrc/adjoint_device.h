@@ -429,33 +429,62 @@ __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, floa
 }
 
 // Pass 2 for one control point (cx, cy, cz): fixed-order sum of brick partials.
+// Bricks whose voxels meet the point's support [(c-3)d, (c+1)d) on each axis,
+// summed bz, then by, then bx ascending.  When no axis has more than two such
+// bricks (bricks of at least 3 tiles) all 8 loads are issued at once from
+// clamped addresses and the valid ones added in that order; otherwise a loop.
+struct AdjSpan {
+  int lo, hi;  // brick range
+};
+
+__device__ __forceinline__ AdjSpan adj_span(const AdjAxis& ax, int c, int d, int n) {
+  return AdjSpan{adj_brick_of_voxel(ax, max(0, (c - 3) * d)), adj_brick_of_voxel(ax, min(n, (c + 1) * d) - 1)};
+}
+
 __device__ __forceinline__ F3 adj_gather_point(const float* __restrict__ part, const AdjGeom& a, int cx,
                                                int cy, int cz) {
   const VolGeom& g = a.g;
-  // bricks whose voxels meet the point's support [(c-3)d, (c+1)d) on each axis
-  const int bxlo = adj_brick_of_voxel(a.x, max(0, (cx - 3) * g.dx));
-  const int bxhi = adj_brick_of_voxel(a.x, min(g.nx, (cx + 1) * g.dx) - 1);
-  const int bylo = adj_brick_of_voxel(a.y, max(0, (cy - 3) * g.dy));
-  const int byhi = adj_brick_of_voxel(a.y, min(g.ny, (cy + 1) * g.dy) - 1);
-  const int bzlo = adj_brick_of_voxel(a.z, max(0, (cz - 3) * g.dz));
-  const int bzhi = adj_brick_of_voxel(a.z, min(g.nz, (cz + 1) * g.dz) - 1);
+  const AdjSpan sx = adj_span(a.x, cx, g.dx, g.nx), sy = adj_span(a.y, cy, g.dy, g.ny),
+                sz = adj_span(a.z, cz, g.dz, g.nz);
   const size_t bstride = (size_t)a.z.cm * a.y.cm * a.x.cm * 3;
-  F3 s{0.f, 0.f, 0.f};
-  for (int bz = bzlo; bz <= bzhi; ++bz) {
+  auto addr = [&](int bx, int by, int bz) {
+    const int cxl = cx - adj_brick_begin(a.x, g.nx, bx) / g.dx;
+    const int cyl = cy - adj_brick_begin(a.y, g.ny, by) / g.dy;
     const int czl = cz - adj_brick_begin(a.z, g.nz, bz) / g.dz;
-    for (int by = bylo; by <= byhi; ++by) {
-      const int cyl = cy - adj_brick_begin(a.y, g.ny, by) / g.dy;
-      for (int bx = bxlo; bx <= bxhi; ++bx) {
-        const int cxl = cx - adj_brick_begin(a.x, g.nx, bx) / g.dx;
-        const float* p = part + (size_t)((bz * a.y.nb + by) * a.x.nb + bx) * bstride +
-                         ((size_t)(czl * a.y.cm + cyl) * a.x.cm + cxl) * 3;
-        const F3 v = ldf3(p);
+    return part + (size_t)((bz * a.y.nb + by) * a.x.nb + bx) * bstride +
+           ((size_t)(czl * a.y.cm + cyl) * a.x.cm + cxl) * 3;
+  };
+  F3 s{0.f, 0.f, 0.f};
+  if (sx.hi - sx.lo <= 1 && sy.hi - sy.lo <= 1 && sz.hi - sz.lo <= 1) {
+    F3 v[2][2][2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+          v[k][j][i] = ldf3(addr(min(sx.lo + i, sx.hi), min(sy.lo + j, sy.hi), min(sz.lo + k, sz.hi)));
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+          if (sz.lo + k <= sz.hi && sy.lo + j <= sy.hi && sx.lo + i <= sx.hi) {
+            s.x += v[k][j][i].x;
+            s.y += v[k][j][i].y;
+            s.z += v[k][j][i].z;
+          }
+    return s;
+  }
+  for (int bz = sz.lo; bz <= sz.hi; ++bz)
+    for (int by = sy.lo; by <= sy.hi; ++by)
+      for (int bx = sx.lo; bx <= sx.hi; ++bx) {
+        const F3 v = ldf3(addr(bx, by, bz));
         s.x += v.x;
         s.y += v.y;
         s.z += v.z;
       }
-    }
-  }
   return s;
 }
 
