@@ -48,7 +48,9 @@ extern "C" {
 
 #define BSI_OK 0
 #define BSI_ERR_INVALID_ARG (-1) /* null pointer, n < 1, d < 1, bad size     */
-#define BSI_ERR_UNSUPPORTED (-2) /* d > BSI_MAX_SPACING, or a size too large  */
+#define BSI_ERR_UNSUPPORTED (-2) /* d > BSI_MAX_SPACING, or a size too large
+                                    (an axis above BSI_MAX_DIM, or a voxel plane
+                                    nx * ny of 2^32 / 3 voxels or more)      */
 #define BSI_ERR_HIP (-3)         /* a HIP call failed; see bsi_last_error()  */
 #define BSI_ERR_NO_DEVICE (-4)   /* no HIP device is visible                 */
 #define BSI_ERR_NOMEM (-5)       /* allocation of a batched plan failed      */

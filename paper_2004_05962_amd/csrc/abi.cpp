@@ -73,6 +73,11 @@ int32_t make_geom(const int32_t dims[3], const int32_t spacing[3], VolGeom* g) {
     set_error("volume too large");
     return BSI_ERR_UNSUPPORTED;
   }
+  // Offsets within one voxel plane of the field are 32-bit in the kernels.
+  if ((double)g->nx * g->ny * 3 >= 4294967296.0) {
+    set_error("a voxel plane (nx * ny) above 1.43e9 voxels");
+    return BSI_ERR_UNSUPPORTED;
+  }
   return BSI_OK;
 }
 

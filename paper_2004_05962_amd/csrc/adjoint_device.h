@@ -236,21 +236,29 @@ __device__ __forceinline__ void adj_xmoment_step(int o, const float* __restrict_
 // v = row * kAdjTilesX * DX + x; lane j loads v = k * 64 + j (k < DX), i.e.
 // consecutive lanes read consecutive 12-byte voxels.
 template <int DX>
-__device__ __forceinline__ void adj_plane_load(const float* __restrict__ plane, const AdjBrick& b, int nx,
-                                               int ywave, int lane, F3 (&d)[DX]) {
+__device__ __forceinline__ void adj_plane_offsets(const AdjBrick& b, int nx, int ywave, int lane,
+                                                  uint32_t (&off)[DX]) {
   // Every lane loads from a valid address, clamped into the brick, with no
   // branch or select around the load (the data is only consumed one plane
   // later).  A clamped slot holds a copy of another voxel, but no lane reads
   // it: tile rows stop at the volume (nval) and rows outside the brick belong
-  // to idle lanes.
+  // to idle lanes.  The offsets (in floats, within a voxel plane) are the same
+  // for every plane of the brick, so they are formed once.
 #pragma unroll
   for (int k = 0; k < DX; ++k) {
     const int v = k * kWave + lane;
     const int r = v / (kAdjTilesX * DX);
     const int xl = v - r * (kAdjTilesX * DX);
     const int x = min(b.x0 + xl, b.xe - 1), y = min(ywave + r, b.ye - 1);
-    d[k] = ldf3(plane + ((size_t)y * nx + x) * 3);
+    off[k] = ((uint32_t)y * (uint32_t)nx + (uint32_t)x) * 3u;  // a plane holds < 2^32 floats (make_geom)
   }
+}
+
+template <int DX>
+__device__ __forceinline__ void adj_plane_load(const float* __restrict__ plane, const uint32_t (&off)[DX],
+                                               F3 (&d)[DX]) {
+#pragma unroll
+  for (int k = 0; k < DX; ++k) d[k] = ldf3(plane + off[k]);
 }
 
 // Stage a loaded plane in the wave's LDS region (lanes exchange data: tile rows
@@ -399,10 +407,12 @@ __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, floa
     // then read back this lane's tile row and reduce it.  One plane of loads is
     // always in flight while the previous one is reduced (and emitted).
     F3 d[DX];
-    adj_plane_load<DX>(plane0, b, g.nx, ywave, lane, d);
+    uint32_t off[DX];
+    adj_plane_offsets<DX>(b, g.nx, ywave, lane, off);
+    adj_plane_load<DX>(plane0, off, d);
     for (int z = b.z0; z < b.ze; ++z) {
       adj_plane_stage<DX>(wbuf, lane, d);
-      if (z + 1 < b.ze) adj_plane_load<DX>(plane0 + (size_t)(z + 1 - b.z0) * zs, b, g.nx, ywave, lane, d);
+      if (z + 1 < b.ze) adj_plane_load<DX>(plane0 + (size_t)(z + 1 - b.z0) * zs, off, d);
       F3 M[4];
       adj_plane_moments<DX>(wbuf, lane, nval, lutx, M);
       step(M, z);

@@ -159,17 +159,23 @@ template <int C>
 __device__ __forceinline__ FwdVal<C> fwd_contract(const float* __restrict__ slot, int base, float bx0,
                                                   float bx1, float bx2, float bx3,
                                                   const float* __restrict__ wy) {
+  // row 0 outside the rolled loop: q = By_0 * row0, then q = fma(By_m, row_m, q)
   FwdVal<C> q;
+  {
+    const float* p = slot + base;
+    const float b = wy[0];
 #pragma unroll
-  for (int c = 0; c < C; ++c) q.v[c] = 0.f;
+    for (int c = 0; c < C; ++c)
+      q.v[c] = b * fmaf(bx3, p[3 * C + c], fmaf(bx2, p[2 * C + c], fmaf(bx1, p[C + c], bx0 * p[c])));
+  }
 #pragma unroll 1
-  for (int m = 0; m < 4; ++m) {
+  for (int m = 1; m < 4; ++m) {
     const float* p = slot + base + m * fwd_pitch<C>();
     const float b = wy[m];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       const float r = fmaf(bx3, p[3 * C + c], fmaf(bx2, p[2 * C + c], fmaf(bx1, p[C + c], bx0 * p[c])));
-      q.v[c] = m == 0 ? b * r : fmaf(b, r, q.v[c]);
+      q.v[c] = fmaf(b, r, q.v[c]);
     }
   }
   return q;

@@ -55,6 +55,7 @@ def test_grid_dims(dims, spacing, expect):
     ((4, 4, 4), (1, 0, 1), _lib.BSI_ERR_INVALID_ARG),
     ((4, 4, 4), (1, 1, 65), _lib.BSI_ERR_UNSUPPORTED),
     ((1 << 21, 4, 4), (1, 1, 1), _lib.BSI_ERR_UNSUPPORTED),
+    ((1 << 20, 1 << 11, 1), (1, 1, 1), _lib.BSI_ERR_UNSUPPORTED),   # a voxel plane of 2^32 * 3/2 floats
 ])
 def test_bad_geometry(dims, spacing, code):
     with pytest.raises(bsi.BSIError) as e:
