@@ -151,13 +151,14 @@ __device__ __forceinline__ void adj_emit(const AdjGeom& a, const AdjBrick& b, fl
 
   __syncthreads();
   const int npend = (k & 1) ? 2 : 1;  // planes k-1, k  or  k alone
-  // item -> (plane p, window row cyl, window column cxl), cxl = item % 32
-  for (int it = tid; it < npend * b.Cy * 32; it += kAdjThreads) {
-    const int cxl = it & 31;
-    const int pc = it >> 5;
-    const int p = pc >= b.Cy ? 1 : 0;
-    const int cyl = pc - p * b.Cy;
-    if (cxl >= b.Cx) continue;
+  // item -> (plane p, window row cyl, window column cxl < Cx): every thread
+  // of a round has an item (Cx <= 19 columns, not a 32-wide slot)
+  const int per_plane = b.Cy * b.Cx;
+  for (int it = tid; it < npend * per_plane; it += kAdjThreads) {
+    const int p = it >= per_plane ? 1 : 0;
+    const int r = it - p * per_plane;
+    const int cyl = r / b.Cx;
+    const int cxl = r - cyl * b.Cx;
     const int kk = k - (npend - 1) + p;
     const float* sp = sm.Sx + (kk % kAdjSlotsX) * (kAdjMaxY * kAdjMaxCx * 3) + cxl * 3;
     const float* wrow = sm.WYC + cyl * kAdjMaxY;
