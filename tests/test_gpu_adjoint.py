@@ -155,3 +155,44 @@ def test_split_passes_bit_identical(dims, spacing):
         bsi.bsi_adjoint_partials(d, dims, spacing, small)
     with pytest.raises(bsi.BSIError):
         bsi.bsi_adjoint_reduce(small, dims, spacing, split)
+
+
+def test_adjoint_full_size_sampled():
+    """The benchmark's configuration (512 x 512 x 256, spacing 5, the same
+    partials + reduce launches) against the oracle's per-control-point gather at
+    sampled control points, the grid's corners included."""
+    case = workloads.cfg2(5)
+    dims, spacing = case["dims"], case["spacing"]
+    say("adjoint 512x512x256 delta 5 sampled")
+    dfield = workloads.random_field(dims, 1.0, seed=1102)
+    d = dev(dfield)
+    ws = torch.empty(bsi.bsi_adjoint_workspace_size(dims, spacing), dtype=torch.uint8, device="cuda")
+    grad = torch.empty(bsi.grid_shape(dims, spacing), device="cuda")
+    bsi.bsi_adjoint_partials(d, dims, spacing, ws)
+    bsi.bsi_adjoint_reduce(ws, dims, spacing, grad)
+    gx, gy, gz = bsi.bsi_grid_dims(dims, spacing)
+    rng = np.random.default_rng(55)
+    cps = np.stack([rng.integers(0, n, 300) for n in (gx, gy, gz)], axis=1)
+    corners = np.array([[x, y, z] for x in (0, gx - 1) for y in (0, gy - 1) for z in (0, gz - 1)])
+    cps = np.concatenate([cps, corners])
+    ref = oracle.adjoint_points(dfield, dims, spacing, cps)
+    got = host(grad)[cps[:, 2], cps[:, 1], cps[:, 0]]
+    assert max_abs(got, ref) <= 1e-5 * float(np.abs(ref).max())
+    again = torch.empty_like(grad)
+    bsi.bsi_adjoint(d, dims, spacing, again, ws)
+    assert torch.equal(grad, again)
+
+
+@pytest.mark.parametrize("dims,spacing", [((65536, 3, 2), (7, 1, 2)), ((2, 65536, 3), (1, 5, 1)),
+                                          ((3, 2, 65536), (2, 1, 6))])
+def test_extreme_aspect_forward_and_adjoint(dims, spacing):
+    """A 65536-voxel axis with two tiny ones: many bricks along one axis, one
+    along the others, partial tiles and partial strips everywhere."""
+    say("extreme aspect", dims, spacing)
+    grid = workloads.random_grid(dims, spacing, 2.0, seed=sum(dims))
+    f = host(bsi.forward(dev(grid), dims, spacing))
+    assert max_abs(f, oracle.forward(grid, dims, spacing)) <= 1e-5 * float(np.abs(grid).max())
+    dfield = workloads.random_field(dims, 1.0, seed=sum(dims) + 1)
+    g = host(bsi.adjoint(dev(dfield), dims, spacing))
+    ref = oracle.adjoint(dfield, dims, spacing)
+    assert max_abs(g, ref) <= 1e-5 * float(np.abs(ref).max())
