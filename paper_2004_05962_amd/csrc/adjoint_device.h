@@ -83,16 +83,6 @@ struct AdjSmem {
 };
 
 
-// Order this wave's LDS writes before its following LDS reads (and vice versa):
-// lanes exchange data through the wave's own region, no workgroup barrier.
-// The fences name the LDS ("local") address space only: a fence without an
-// address space would also order global memory, i.e. wait for the wave's
-// outstanding prefetch loads.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-}
 
 struct AdjBrick {
   int x0, y0, z0, xe, ye, ze;  // voxel range [x0, xe) etc.

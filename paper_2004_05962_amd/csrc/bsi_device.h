@@ -69,6 +69,17 @@ __device__ __forceinline__ int xcd_remap(int id, int n) {
   return xcd * q + (xcd < r ? xcd : r) + k;
 }
 
+// Order this wave's LDS writes before its following LDS reads (and vice versa):
+// lanes exchange data through the wave's own region, no workgroup barrier.
+// The fences name the LDS ("local") address space only: a fence without an
+// address space would also order global memory, i.e. wait for the wave's
+// outstanding prefetch loads.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
 __device__ __forceinline__ F3 ldf3(const float* p) { return *reinterpret_cast<const F3*>(p); }
 __device__ __forceinline__ void stf3(float* p, F3 v) { *reinterpret_cast<F3*>(p) = v; }
 

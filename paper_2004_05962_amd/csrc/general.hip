@@ -188,11 +188,90 @@ __global__ __launch_bounds__(256) void gen_gather_kernel(const float* __restrict
   dst[2] = sz;
 }
 
+// First voxel of every x tile: first[t] = min{v : i(v) >= t} for t = 0..g
+// (first[g] = n), from the nondecreasing table of window starts.
+__global__ __launch_bounds__(256) void gen_first_kernel(GenAxis a, const int* __restrict__ tile,
+                                                         int* __restrict__ first) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t > a.g) return;
+  int lo = 0, hi = a.n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (tile[mid] < t) lo = mid + 1;
+    else hi = mid;
+  }
+  first[t] = lo;
+}
+
+// The x pass of the adjoint by tile moments.  Along x, tile t is the run of
+// voxels [first[t], first[t+1]), and output c = sum_l M_l(c - l) (l ascending)
+// with M_l(t) = sum_{v in tile t} B_l(u(v)) d(v) (v ascending).  A wave takes
+// one row and kGxTiles consecutive tiles t0 .. t0+63 (t0 = c0 - 3): lane j
+// forms the moments of tile t0 + j from global memory (its tile's voxels are
+// contiguous, so the wave's loads cover a contiguous run), publishes them in
+// the wave's LDS region, and lanes j < kGxTiles - 3 then form output c0 + j.
+constexpr int kGxRows = 4;                 // rows per workgroup, one per wave
+constexpr int kGxThreads = kGxRows * kWave;
+constexpr int kGxTiles = kWave;            // tiles per wave
+constexpr int kGxOut = kGxTiles - 3;       // outputs per wave
+
+__global__ __launch_bounds__(kGxThreads) void gen_gather_x_kernel(const float* __restrict__ in,
+                                                                   float* __restrict__ out, GenAxis a,
+                                                                   const int* __restrict__ first,
+                                                                   const float* __restrict__ w, long rows) {
+  __shared__ float sm[kGxRows][kGxTiles * 12];
+  const int nseg = (a.g + kGxOut - 1) / kGxOut;
+  const long rblk = blockIdx.x / nseg;
+  const int seg = blockIdx.x - (int)(rblk * nseg);
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const long row = rblk * kGxRows + wave;
+  if (row >= rows) return;  // wave-uniform; no workgroup barrier below
+  const int c0 = seg * kGxOut;
+  const int t = c0 - 3 + lane;  // this lane's tile
+  float mm[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) mm[k] = 0.f;
+  if (t >= 0 && t < a.g - 3) {  // tiles 0 .. g-4 hold voxels
+    const float* src = in + (size_t)row * a.n * 3;
+    const int v1 = first[t + 1];
+    for (int v = first[t]; v < v1; ++v) {
+      const F3 d = ldf3(src + (size_t)v * 3);
+      const float* pw = w + 4 * v;
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        mm[3 * l] = fmaf(pw[l], d.x, mm[3 * l]);
+        mm[3 * l + 1] = fmaf(pw[l], d.y, mm[3 * l + 1]);
+        mm[3 * l + 2] = fmaf(pw[l], d.z, mm[3 * l + 2]);
+      }
+    }
+  }
+  float* mv = sm[wave];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) mv[lane * 12 + k] = mm[k];
+  wave_lds_sync();
+  const int c = c0 + lane;
+  if (lane < kGxOut && c < a.g) {
+    float sx = 0.f, sy = 0.f, sz = 0.f;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      const float* m = mv + (lane + 3 - l) * 12 + 3 * l;  // tile c - l (zero when it has no voxels)
+      sx += m[0];
+      sy += m[1];
+      sz += m[2];
+    }
+    float* dst = out + ((size_t)row * a.g + c) * 3;
+    dst[0] = sx;
+    dst[1] = sy;
+    dst[2] = sz;
+  }
+}
+
 constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 struct GenWork {
   int* tile[3];
   float* w[3];
+  int* first;  // first voxel of every x tile (gx + 1 entries)
   float* A;   // [nz][ny][gx][3]
   float* Bm;  // [nz][gy][gx][3]
 };
@@ -207,6 +286,8 @@ size_t gen_layout(const GenGeom& q, void* base, GenWork* wk) {
     if (wk) wk->w[i] = reinterpret_cast<float*>(p + off);
     off += align256((size_t)ax[i]->n * 4 * sizeof(float));
   }
+  if (wk) wk->first = reinterpret_cast<int*>(p + off);
+  off += align256((size_t)(q.x.g + 1) * sizeof(int));
   if (wk) wk->A = reinterpret_cast<float*>(p + off);
   off += align256((size_t)q.z.n * q.y.n * q.x.g * 3 * sizeof(float));
   if (wk) wk->Bm = reinterpret_cast<float*>(p + off);
@@ -280,11 +361,18 @@ hipError_t launch_adjoint_general(const float* dfield, float* grad, const GenGeo
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  // x: [nz*ny][nx][1] -> A [nz*ny][gx][1]
-  const long rows = (long)q.z.n * q.y.n;
-  hipLaunchKernelGGL(gen_gather_kernel, dim3(blocks_for(rows * q.x.g)), dim3(256), 0, s, dfield, wk.A, q.x,
-                     wk.tile[0], wk.w[0], rows, 1);
+  // x: [nz*ny][nx] -> A [nz*ny][gx] by tile moments: kGxRows rows and kGxOut
+  // outputs per workgroup
+  hipLaunchKernelGGL(gen_first_kernel, dim3(blocks_for(q.x.g + 1)), dim3(256), 0, s, q.x, wk.tile[0], wk.first);
   hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const long rows = (long)q.z.n * q.y.n;
+  const long nseg = (q.x.g + kGxOut - 1) / kGxOut;
+  const long blocks = (rows + kGxRows - 1) / kGxRows * nseg;
+  if (blocks > 0x7fffffffL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(gen_gather_x_kernel, dim3((unsigned)blocks), dim3(kGxThreads), 0, s, dfield, wk.A, q.x,
+                     wk.first, wk.w[0], rows);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   // y: [nz][ny][gx] -> Bm [nz][gy][gx]
   hipLaunchKernelGGL(gen_gather_kernel, dim3(blocks_for((long)q.z.n * q.y.g * q.x.g)), dim3(256), 0, s, wk.A,
