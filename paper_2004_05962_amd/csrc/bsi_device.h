@@ -99,7 +99,8 @@ __device__ __forceinline__ void stf3(float* p, F3 v) { *reinterpret_cast<F3*>(p)
 // two-slot LDS ring: the next plane is loaded into registers (a few floats per
 // thread, coalesced rows) while the current tile is written, then stored to the
 // free slot; one barrier per tile.  Each voxel is one 12-byte store, so a wave
-// writes 768 contiguous bytes per plane.
+// writes 768 contiguous bytes per plane.  For scalar images a lane owns 4
+// consecutive voxels instead (one 16-byte store; a wave writes 1 KB per plane).
 // ----------------------------------------------------------------------------
 #ifndef BSI_FWD_ROWS
 #define BSI_FWD_ROWS 4
@@ -108,53 +109,57 @@ constexpr int kFwdRows = BSI_FWD_ROWS;                 // waves (rows) per workg
 constexpr int kFwdThreads = kWave * kFwdRows;
 constexpr int kFwdMaxCx = (kWave - 1) + 4;             // window width at spacing 1
 constexpr int kFwdMaxCy = (kFwdRows - 1) + 4;          // window height at spacing 1
+// A lane may own V consecutive x-voxels (a wave then covers 64 V voxels of its
+// row): the staged window widens to 64 V + 3 points at spacing 1.
+template <int V>
+__host__ __device__ constexpr int fwd_max_cx() { return kWave * V - 1 + 4; }
 // Staged window of one control plane for C components per point.
-template <int C>
-__host__ __device__ constexpr int fwd_pitch() { return kFwdMaxCx * C; }  // floats per staged control row
-template <int C>
+template <int C, int V = 1>
+__host__ __device__ constexpr int fwd_pitch() { return fwd_max_cx<V>() * C; }  // floats per staged control row
+template <int C, int V = 1>
 __host__ __device__ constexpr int fwd_loads() {  // staged floats per thread
-  return (kFwdMaxCy * fwd_pitch<C>() + kFwdThreads - 1) / kFwdThreads;
+  return (kFwdMaxCy * fwd_pitch<C, V>() + kFwdThreads - 1) / kFwdThreads;
 }
 
-template <int C>
+template <int C, int V = 1>
 struct FwdSmem {
-  float ring[2][fwd_loads<C>() * kFwdThreads];
+  float ring[2][fwd_loads<C, V>() * kFwdThreads];
 };
 
 // Staging map: thread tid moves floats e = tid + k * kFwdThreads of the window,
 // e = row * pitch + col; goff[k] is its grid offset within a plane, or -1 when
 // e lies outside this workgroup's window.
-template <int C>
+template <int C, int V = 1>
 struct FwdStage {
-  int goff[fwd_loads<C>()];
+  int goff[fwd_loads<C, V>()];
 };
 
-template <int C>
-__device__ __forceinline__ FwdStage<C> fwd_stage_map(const VolGeom& g, int cx0, int ncx, int cy0, int ncy,
-                                                     int tid) {
-  FwdStage<C> m;
+template <int C, int V = 1>
+__device__ __forceinline__ FwdStage<C, V> fwd_stage_map(const VolGeom& g, int cx0, int ncx, int cy0, int ncy,
+                                                        int tid) {
+  FwdStage<C, V> m;
 #pragma unroll
-  for (int k = 0; k < fwd_loads<C>(); ++k) {
+  for (int k = 0; k < fwd_loads<C, V>(); ++k) {
     const int e = tid + k * kFwdThreads;
-    const int row = e / fwd_pitch<C>();
-    const int col = e - row * fwd_pitch<C>();
+    const int row = e / fwd_pitch<C, V>();
+    const int col = e - row * fwd_pitch<C, V>();
     m.goff[k] = (row < ncy && col < ncx * C) ? ((cy0 + row) * g.gx + cx0) * C + col : -1;
   }
   return m;
 }
 
-template <int C>
+template <int C, int V = 1>
 __device__ __forceinline__ void fwd_fetch(const float* __restrict__ grid, const VolGeom& g,
-                                          const FwdStage<C>& m, int cz, float (&r)[fwd_loads<C>()]) {
+                                          const FwdStage<C, V>& m, int cz, float (&r)[fwd_loads<C, V>()]) {
   const float* plane = grid + (size_t)cz * g.gy * g.gx * C;
 #pragma unroll
-  for (int k = 0; k < fwd_loads<C>(); ++k) r[k] = m.goff[k] >= 0 ? plane[m.goff[k]] : 0.f;
+  for (int k = 0; k < fwd_loads<C, V>(); ++k) r[k] = m.goff[k] >= 0 ? plane[m.goff[k]] : 0.f;
 }
 
-template <int C>
-__device__ __forceinline__ void fwd_stage(float* __restrict__ slot, int tid, const float (&r)[fwd_loads<C>()]) {
+template <int C, int V = 1>
+__device__ __forceinline__ void fwd_stage(float* __restrict__ slot, int tid, const float (&r)[fwd_loads<C, V>()]) {
 #pragma unroll
-  for (int k = 0; k < fwd_loads<C>(); ++k) slot[tid + k * kFwdThreads] = r[k];
+  for (int k = 0; k < fwd_loads<C, V>(); ++k) slot[tid + k * kFwdThreads] = r[k];
 }
 
 template <int C>
@@ -166,7 +171,7 @@ struct FwdVal {
 // 4 control rows, then the y-contraction with weights wy[0..3].  The row loop is
 // kept rolled so only one row is in flight: a small register footprint, i.e.
 // more waves per SIMD to hide LDS and memory latency.
-template <int C>
+template <int C, int V = 1>
 __device__ __forceinline__ FwdVal<C> fwd_contract(const float* __restrict__ slot, int base, float bx0,
                                                   float bx1, float bx2, float bx3,
                                                   const float* __restrict__ wy) {
@@ -181,7 +186,7 @@ __device__ __forceinline__ FwdVal<C> fwd_contract(const float* __restrict__ slot
   }
 #pragma unroll 1
   for (int m = 1; m < 4; ++m) {
-    const float* p = slot + base + m * fwd_pitch<C>();
+    const float* p = slot + base + m * fwd_pitch<C, V>();
     const float b = wy[m];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -202,89 +207,133 @@ __device__ __forceinline__ void fwd_store(float* p, const float (&t)[C]) {
   for (int c = 0; c < C; ++c) __builtin_nontemporal_store(t[c], p + c);
 }
 
+typedef float fwd_f4 __attribute__((ext_vector_type(4)));
+
 // Collective over the workgroup (kFwdThreads threads, all bounds uniform).
-// C = 3 for displacement grids, C = 1 for scalar images.
-template <int C>
+// C = 3 for displacement grids, C = 1 for scalar images.  Lane j owns the V
+// consecutive voxels x0 + V j .. x0 + V j + V - 1 of its row; each voxel goes
+// through exactly the same operations whatever V is.  V = 4 (C = 1 only)
+// requires every row to start on a 16-byte boundary: a lane whose 4 voxels all
+// lie in the volume writes them with one 16-byte store.
+template <int C, int V = 1>
 __device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float* __restrict__ field,
                                           const VolGeom& g, const float* __restrict__ lut, int x0, int y0,
-                                          int z0, int z1, FwdSmem<C>& sm, int tid) {
+                                          int z0, int z1, FwdSmem<C, V>& sm, int tid) {
+  static_assert(V == 1 || (V == 4 && C == 1), "wide lanes are for scalar images");
   const int lane = tid & (kWave - 1);
   const int wave = uniform(tid / kWave);
   const int cx0 = x0 / g.dx;
-  const int ncx = (min(x0 + kWave, g.nx) - 1) / g.dx - cx0 + 4;
+  const int ncx = (min(x0 + kWave * V, g.nx) - 1) / g.dx - cx0 + 4;
   const int cy0 = y0 / g.dy;
   const int ncy = (min(y0 + kFwdRows, g.ny) - 1) / g.dy - cy0 + 4;
-  const FwdStage<C> map = fwd_stage_map<C>(g, cx0, ncx, cy0, ncy, tid);
+  const FwdStage<C, V> map = fwd_stage_map<C, V>(g, cx0, ncx, cy0, ncy, tid);
 
-  const int x = x0 + lane;
+  const int xl = x0 + V * lane;  // the lane's first voxel
   const int y = y0 + wave;
-  const bool active = x < g.nx && y < g.ny;
-  const int xc = min(x, g.nx - 1);  // idle lanes read a valid column, store nothing
   const int yc = min(y, g.ny - 1);
-  const int tx = xc / g.dx;
-  const int ox = xc - tx * g.dx;
   const int ty = yc / g.dy;
   const int oy = yc - ty * g.dy;
-  const float* wx = lut_row(lut, g.dx, ox);
-  const float bx0 = wx[0], bx1 = wx[1], bx2 = wx[2], bx3 = wx[3];
   const float* wy = lut_row(lut, g.dy, oy);  // wave-uniform
-  const int base = (ty - cy0) * fwd_pitch<C>() + (tx - cx0) * C;
+  bool active[V];
+  float bx[V][4];
+  int base[V];
+#pragma unroll
+  for (int k = 0; k < V; ++k) {
+    const int x = xl + k;
+    active[k] = x < g.nx && y < g.ny;
+    const int xc = min(x, g.nx - 1);  // idle lanes read a valid column, store nothing
+    const int tx = xc / g.dx;
+    const float* wx = lut_row(lut, g.dx, xc - tx * g.dx);
+#pragma unroll
+    for (int l = 0; l < 4; ++l) bx[k][l] = wx[l];
+    base[k] = (ty - cy0) * fwd_pitch<C, V>() + (tx - cx0) * C;
+  }
+  auto contract = [&](const float* slot, int k) {
+    return fwd_contract<C, V>(slot, base[k], bx[k][0], bx[k][1], bx[k][2], bx[k][3], wy);
+  };
 
   int tz = z0 / g.dz;
   int oz = z0 - tz * g.dz;
-  float r[fwd_loads<C>()];
+  float r[fwd_loads<C, V>()];
   // Warm-up: stage planes tz, tz+1, tz+2 one at a time (slots 0, 1, 0) and shift
   // their contractions into q0..q2; then stage plane tz+3 into slot 1 (its
   // contraction is the loop head).  One plane in flight keeps registers low.
-  FwdVal<C> q0, q1, q2;
+  FwdVal<C> q0[V], q1[V], q2[V];
 #pragma unroll
-  for (int c = 0; c < C; ++c) q0.v[c] = q1.v[c] = q2.v[c] = 0.f;
+  for (int k = 0; k < V; ++k)
+#pragma unroll
+    for (int c = 0; c < C; ++c) q0[k].v[c] = q1[k].v[c] = q2[k].v[c] = 0.f;
 #pragma unroll 1
   for (int j = 0; j < 3; ++j) {
     __syncthreads();  // the slot may still be read (previous item or iteration)
-    fwd_fetch<C>(grid, g, map, tz + j, r);
-    fwd_stage<C>(sm.ring[j & 1], tid, r);
+    fwd_fetch<C, V>(grid, g, map, tz + j, r);
+    fwd_stage<C, V>(sm.ring[j & 1], tid, r);
     __syncthreads();
-    const FwdVal<C> qn = fwd_contract<C>(sm.ring[j & 1], base, bx0, bx1, bx2, bx3, wy);
-    q0 = q1;
-    q1 = q2;
-    q2 = qn;
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      const FwdVal<C> qn = contract(sm.ring[j & 1], k);
+      q0[k] = q1[k];
+      q1[k] = q2[k];
+      q2[k] = qn;
+    }
   }
   __syncthreads();
-  fwd_fetch<C>(grid, g, map, tz + 3, r);
-  fwd_stage<C>(sm.ring[1], tid, r);
+  fwd_fetch<C, V>(grid, g, map, tz + 3, r);
+  fwd_stage<C, V>(sm.ring[1], tid, r);
   __syncthreads();
   int slot3 = 1;  // slot holding plane tz + 3
 
   const size_t zstride = (size_t)g.ny * g.nx * C;
-  float* out = field + (((size_t)z0 * g.ny + yc) * g.nx + xc) * C;
+  float* out = field + (((size_t)z0 * g.ny + yc) * g.nx + min(xl, g.nx - 1)) * C;
+  bool all = true;
+#pragma unroll
+  for (int k = 0; k < V; ++k) all = all && active[k];
+  const bool wide = V == 4 && all;
   int z = z0;
   for (;;) {
-    const FwdVal<C> q3 = fwd_contract<C>(sm.ring[slot3], base, bx0, bx1, bx2, bx3, wy);
+    FwdVal<C> q3[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) q3[k] = contract(sm.ring[slot3], k);
     const int left = z1 - z;
     const bool more = g.dz - oz < left;  // another tile follows inside this range
     // its new plane tz + 4 is then at most ceil(nz/dz) + 2 = gz - 1: in bounds
-    if (more) fwd_fetch<C>(grid, g, map, tz + 4, r);
+    if (more) fwd_fetch<C, V>(grid, g, map, tz + 4, r);
     const int oend = more ? g.dz : oz + left;
     for (; oz < oend; ++oz, ++z) {
       const float* wz = lut_row(lut, g.dz, oz);
       const float w0 = wz[0], w1 = wz[1], w2 = wz[2], w3 = wz[3];
-      float t[C];
+      float t[V][C];
 #pragma unroll
-      for (int c = 0; c < C; ++c) t[c] = fmaf(w3, q3.v[c], fmaf(w2, q2.v[c], fmaf(w1, q1.v[c], w0 * q0.v[c])));
-      if (active) fwd_store<C>(out, t);
+      for (int k = 0; k < V; ++k)
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+          t[k][c] = fmaf(w3, q3[k].v[c], fmaf(w2, q2[k].v[c], fmaf(w1, q1[k].v[c], w0 * q0[k].v[c])));
+      if constexpr (V == 4) {
+        if (wide) {
+          __builtin_nontemporal_store(fwd_f4{t[0][0], t[1][0], t[2][0], t[3][0]}, reinterpret_cast<fwd_f4*>(out));
+        } else {
+#pragma unroll
+          for (int k = 0; k < V; ++k)
+            if (active[k]) fwd_store<C>(out + k * C, t[k]);
+        }
+      } else {
+        if (active[0]) fwd_store<C>(out, t[0]);
+      }
       out += zstride;
     }
     if (!more) break;
     // plane tz + 4 goes to the slot of plane tz + 2, consumed one tile ago
-    fwd_stage<C>(sm.ring[slot3 ^ 1], tid, r);
+    fwd_stage<C, V>(sm.ring[slot3 ^ 1], tid, r);
     __syncthreads();
     slot3 ^= 1;
     oz = 0;
     ++tz;
-    q0 = q1;
-    q1 = q2;
-    q2 = q3;
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      q0[k] = q1[k];
+      q1[k] = q2[k];
+      q2[k] = q3[k];
+    }
   }
 }
 

@@ -1,21 +1,21 @@
 // Forward BSI kernel (Eq. 1) for one volume: C = 3 for a displacement grid,
 // C = 1 for a scalar image (B-spline upsampling).
 //
-// Workgroup = kFwdRows waves = kFwdRows consecutive rows of one 64-voxel x-strip,
-// over one chunk of z; it runs fwd_block (bsi_device.h): per-lane sum
-// factorisation with a rolling window of 4 contracted control planes in
-// registers, control points staged per plane in LDS, and one coalesced 12-byte
-// store per voxel.  The field write is the dominant HBM traffic (12 bytes per
+// Workgroup = kFwdRows waves = kFwdRows consecutive rows of one 64-voxel x-strip
+// (256 voxels, 4 per lane, for scalar images), over one chunk of z; it runs
+// fwd_block (bsi_device.h): per-lane sum factorisation with a rolling window of
+// 4 contracted control planes in registers, control points staged per plane in
+// LDS, and one coalesced 12-byte store per voxel (16 bytes per 4 scalar voxels).  The field write is the dominant HBM traffic (12 bytes per
 // voxel against 12 bytes per control point).
 #include "bsi_internal.h"
 
 namespace bsi {
 
-template <int C>
+template <int C, int V>
 __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(const float* __restrict__ grid,
                                                            float* __restrict__ field, VolGeom g,
                                                            const float* __restrict__ lut, FwdLaunch L) {
-  __shared__ FwdSmem<C> sm;
+  __shared__ FwdSmem<C, V> sm;
   int id = xcd_remap(blockIdx.x, gridDim.x);
   const int bx = id % L.nbx;
   id /= L.nbx;
@@ -23,12 +23,12 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(const float* __restric
   const int bz = id / L.nby;
   const int z0 = bz * L.zchunk;
   const int z1 = min(g.nz, z0 + L.zchunk);
-  fwd_block<C>(grid, field, g, lut, bx * kWave, by * kFwdRows, z0, z1, sm, threadIdx.x);
+  fwd_block<C, V>(grid, field, g, lut, bx * kWave * V, by * kFwdRows, z0, z1, sm, threadIdx.x);
 }
 
-FwdLaunch make_fwd_launch(const VolGeom& g, long target) {
+FwdLaunch make_fwd_launch(const VolGeom& g, long target, int lane_voxels) {
   FwdLaunch L;
-  L.nbx = (g.nx + kWave - 1) / kWave;
+  L.nbx = (g.nx + kWave * lane_voxels - 1) / (kWave * lane_voxels);
   L.nby = (g.ny + kFwdRows - 1) / kFwdRows;
   // Split z (at tile boundaries) until there are >= target workgroups: enough
   // waves to keep the stores flowing, and no more (each chunk restages the 3
@@ -49,17 +49,27 @@ hipError_t launch_forward(const float* grid, float* field, const VolGeom& g, con
                           hipStream_t s) {
   const FwdLaunch L = make_fwd_launch(g);
   const long blocks = (long)L.nbx * L.nby * L.nbz;
-  hipLaunchKernelGGL(fwd_kernel<3>, dim3((unsigned)blocks), dim3(kFwdThreads), 0, s, grid, field, g,
+  hipLaunchKernelGGL((fwd_kernel<3, 1>), dim3((unsigned)blocks), dim3(kFwdThreads), 0, s, grid, field, g,
                      lut, L);
   return hipGetLastError();
 }
 
 hipError_t launch_forward_scalar(const float* grid, float* image, const VolGeom& g, const float* lut,
                                  hipStream_t s) {
-  const FwdLaunch L = make_fwd_launch(g);
-  const long blocks = (long)L.nbx * L.nby * L.nbz;
-  hipLaunchKernelGGL(fwd_kernel<1>, dim3((unsigned)blocks), dim3(kFwdThreads), 0, s, grid, image, g,
-                     lut, L);
+  // Rows starting on 16-byte boundaries: 4 voxels per lane, one 16-byte store
+  // each.  Otherwise one voxel per lane (4 stores per lane would each cover
+  // only every fourth dword of the wave's span).
+  if (g.nx % 4 == 0 && reinterpret_cast<uintptr_t>(image) % 16 == 0) {
+    const FwdLaunch L = make_fwd_launch(g, kFwdTargetBlocks, 4);
+    const long blocks = (long)L.nbx * L.nby * L.nbz;
+    hipLaunchKernelGGL((fwd_kernel<1, 4>), dim3((unsigned)blocks), dim3(kFwdThreads), 0, s, grid, image, g, lut,
+                       L);
+  } else {
+    const FwdLaunch L = make_fwd_launch(g);
+    const long blocks = (long)L.nbx * L.nby * L.nbz;
+    hipLaunchKernelGGL((fwd_kernel<1, 1>), dim3((unsigned)blocks), dim3(kFwdThreads), 0, s, grid, image, g, lut,
+                       L);
+  }
   return hipGetLastError();
 }
 

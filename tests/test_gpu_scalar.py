@@ -42,8 +42,11 @@ def test_scalar_matches_oracle(dims, spacing):
     assert max_abs(host(out), ref) <= 1e-5 * float(np.abs(grid).max())
 
 
-def test_scalar_equals_vector_component_bits():
-    dims, spacing = (77, 45, 31), (5, 4, 6)
+@pytest.mark.parametrize("dims,spacing", [
+    ((77, 45, 31), (5, 4, 6)),      # rows not 16-byte aligned: one voxel per lane
+    ((300, 21, 17), (4, 5, 3)),     # 4 voxels per lane; a partial second 256-voxel strip
+])
+def test_scalar_equals_vector_component_bits(dims, spacing):
     say("scalar vs vector component bits", dims, spacing)
     g3 = torch.randn(bsi.grid_shape(dims, spacing), device="cuda")
     f3 = bsi.forward(g3, dims, spacing)
@@ -81,3 +84,22 @@ def test_scalar_full_size_sampled():
     ref = oracle.forward_points(g3, dims, spacing, pts)[:, 0]
     got = host(img)[pts[:, 2], pts[:, 1], pts[:, 0]]
     assert np.max(np.abs(got - ref)) <= 1e-5 * float(np.abs(grid).max())
+
+
+def test_scalar_unaligned_output_same_bits():
+    # rows of 4k voxels, but the image starts 4 bytes past a 16-byte boundary:
+    # one voxel per lane, same values as the 4-voxels-per-lane path
+    dims, spacing = (136, 19, 14), (5, 3, 4)
+    say("scalar forward, unaligned output", dims, spacing)
+    grid = dev(_grid(dims, spacing, seed=11))
+    nx, ny, nz = dims
+    n = nx * ny * nz
+    aligned = torch.empty((nz, ny, nx), device="cuda")
+    bsi.bsi_forward_scalar(grid, dims, spacing, aligned)
+    buf = torch.full((n + 2,), 1.0e30, device="cuda")
+    out = buf[1:1 + n].view(nz, ny, nx)
+    assert out.data_ptr() % 16 == 4
+    bsi.bsi_forward_scalar(grid, dims, spacing, out)
+    torch.cuda.synchronize()
+    assert torch.equal(out, aligned)
+    assert bool(buf[0] == 1.0e30) and bool(buf[-1] == 1.0e30)  # float32 canaries untouched
