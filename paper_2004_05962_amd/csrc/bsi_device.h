@@ -109,57 +109,64 @@ constexpr int kFwdRows = BSI_FWD_ROWS;                 // waves (rows) per workg
 constexpr int kFwdThreads = kWave * kFwdRows;
 constexpr int kFwdMaxCx = (kWave - 1) + 4;             // window width at spacing 1
 constexpr int kFwdMaxCy = (kFwdRows - 1) + 4;          // window height at spacing 1
-// A lane may own V consecutive x-voxels (a wave then covers 64 V voxels of its
-// row): the staged window widens to 64 V + 3 points at spacing 1.
-template <int V>
-__host__ __device__ constexpr int fwd_max_cx() { return kWave * V - 1 + 4; }
+// Workgroup shape: R rows of S consecutive strips, one wave per (row, strip);
+// a lane owns V consecutive x-voxels, so a strip is 64 V voxels and a
+// workgroup row 64 S V.  The staged window is sized for spacing 1.
+template <int R, int S, int V>
+struct FwdTile {
+  static constexpr int rows = R, strips = S, lane_voxels = V;
+  static constexpr int threads = kWave * R * S;
+  static constexpr int width = kWave * S * V;  // voxels per workgroup row
+  static constexpr int max_cx = width - 1 + 4, max_cy = R - 1 + 4;
+};
+using FwdTileDefault = FwdTile<kFwdRows, 1, 1>;
 // Staged window of one control plane for C components per point.
-template <int C, int V = 1>
-__host__ __device__ constexpr int fwd_pitch() { return fwd_max_cx<V>() * C; }  // floats per staged control row
-template <int C, int V = 1>
+template <int C, class T = FwdTileDefault>
+__host__ __device__ constexpr int fwd_pitch() { return T::max_cx * C; }  // floats per staged control row
+template <int C, class T = FwdTileDefault>
 __host__ __device__ constexpr int fwd_loads() {  // staged floats per thread
-  return (kFwdMaxCy * fwd_pitch<C, V>() + kFwdThreads - 1) / kFwdThreads;
+  return (T::max_cy * fwd_pitch<C, T>() + T::threads - 1) / T::threads;
 }
 
-template <int C, int V = 1>
+template <int C, class T = FwdTileDefault>
 struct FwdSmem {
-  float ring[2][fwd_loads<C, V>() * kFwdThreads];
+  float ring[2][fwd_loads<C, T>() * T::threads];
 };
 
-// Staging map: thread tid moves floats e = tid + k * kFwdThreads of the window,
+// Staging map: thread tid moves floats e = tid + k * threads of the window,
 // e = row * pitch + col; goff[k] is its grid offset within a plane, or -1 when
 // e lies outside this workgroup's window.
-template <int C, int V = 1>
+template <int C, class T = FwdTileDefault>
 struct FwdStage {
-  int goff[fwd_loads<C, V>()];
+  int goff[fwd_loads<C, T>()];
 };
 
-template <int C, int V = 1>
-__device__ __forceinline__ FwdStage<C, V> fwd_stage_map(const VolGeom& g, int cx0, int ncx, int cy0, int ncy,
+template <int C, class T = FwdTileDefault>
+__device__ __forceinline__ FwdStage<C, T> fwd_stage_map(const VolGeom& g, int cx0, int ncx, int cy0, int ncy,
                                                         int tid) {
-  FwdStage<C, V> m;
+  FwdStage<C, T> m;
 #pragma unroll
-  for (int k = 0; k < fwd_loads<C, V>(); ++k) {
-    const int e = tid + k * kFwdThreads;
-    const int row = e / fwd_pitch<C, V>();
-    const int col = e - row * fwd_pitch<C, V>();
+  for (int k = 0; k < fwd_loads<C, T>(); ++k) {
+    const int e = tid + k * T::threads;
+    const int row = e / fwd_pitch<C, T>();
+    const int col = e - row * fwd_pitch<C, T>();
     m.goff[k] = (row < ncy && col < ncx * C) ? ((cy0 + row) * g.gx + cx0) * C + col : -1;
   }
   return m;
 }
 
-template <int C, int V = 1>
+template <int C, class T = FwdTileDefault>
 __device__ __forceinline__ void fwd_fetch(const float* __restrict__ grid, const VolGeom& g,
-                                          const FwdStage<C, V>& m, int cz, float (&r)[fwd_loads<C, V>()]) {
+                                          const FwdStage<C, T>& m, int cz, float (&r)[fwd_loads<C, T>()]) {
   const float* plane = grid + (size_t)cz * g.gy * g.gx * C;
 #pragma unroll
-  for (int k = 0; k < fwd_loads<C, V>(); ++k) r[k] = m.goff[k] >= 0 ? plane[m.goff[k]] : 0.f;
+  for (int k = 0; k < fwd_loads<C, T>(); ++k) r[k] = m.goff[k] >= 0 ? plane[m.goff[k]] : 0.f;
 }
 
-template <int C, int V = 1>
-__device__ __forceinline__ void fwd_stage(float* __restrict__ slot, int tid, const float (&r)[fwd_loads<C, V>()]) {
+template <int C, class T = FwdTileDefault>
+__device__ __forceinline__ void fwd_stage(float* __restrict__ slot, int tid, const float (&r)[fwd_loads<C, T>()]) {
 #pragma unroll
-  for (int k = 0; k < fwd_loads<C, V>(); ++k) slot[tid + k * kFwdThreads] = r[k];
+  for (int k = 0; k < fwd_loads<C, T>(); ++k) slot[tid + k * T::threads] = r[k];
 }
 
 template <int C>
@@ -171,7 +178,7 @@ struct FwdVal {
 // 4 control rows, then the y-contraction with weights wy[0..3].  The row loop is
 // kept rolled so only one row is in flight: a small register footprint, i.e.
 // more waves per SIMD to hide LDS and memory latency.
-template <int C, int V = 1>
+template <int C, class T = FwdTileDefault>
 __device__ __forceinline__ FwdVal<C> fwd_contract(const float* __restrict__ slot, int base, float bx0,
                                                   float bx1, float bx2, float bx3,
                                                   const float* __restrict__ wy) {
@@ -186,7 +193,7 @@ __device__ __forceinline__ FwdVal<C> fwd_contract(const float* __restrict__ slot
   }
 #pragma unroll 1
   for (int m = 1; m < 4; ++m) {
-    const float* p = slot + base + m * fwd_pitch<C, V>();
+    const float* p = slot + base + m * fwd_pitch<C, T>();
     const float b = wy[m];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
@@ -209,27 +216,31 @@ __device__ __forceinline__ void fwd_store(float* p, const float (&t)[C]) {
 
 typedef float fwd_f4 __attribute__((ext_vector_type(4)));
 
-// Collective over the workgroup (kFwdThreads threads, all bounds uniform).
-// C = 3 for displacement grids, C = 1 for scalar images.  Lane j owns the V
-// consecutive voxels x0 + V j .. x0 + V j + V - 1 of its row; each voxel goes
-// through exactly the same operations whatever V is.  V = 4 (C = 1 only)
-// requires every row to start on a 16-byte boundary: a lane whose 4 voxels all
-// lie in the volume writes them with one 16-byte store.
-template <int C, int V = 1>
+// Collective over the workgroup (T::threads threads, all bounds uniform).
+// C = 3 for displacement grids, C = 1 for scalar images.  x0, y0: the
+// workgroup's first voxel and row.  The lane of strip k owns the V consecutive
+// voxels x0 + 64 V k + V lane + (0 .. V-1) of its row; each voxel goes through
+// exactly the same operations whatever the shape.  V = 4 (C = 1 only) requires
+// every row to start on a 16-byte boundary: a lane whose 4 voxels all lie in
+// the volume writes them with one 16-byte store.  Edge (V = 1): lanes whose
+// voxel lies in a 64-byte segment shared with the neighbouring span use
+// ordinary stores (see below); for rows that do not start on 64-byte boundaries.
+template <int C, class T = FwdTileDefault, bool Edge = false>
 __device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float* __restrict__ field,
                                           const VolGeom& g, const float* __restrict__ lut, int x0, int y0,
-                                          int z0, int z1, FwdSmem<C, V>& sm, int tid) {
+                                          int z0, int z1, FwdSmem<C, T>& sm, int tid) {
+  constexpr int V = T::lane_voxels;
   static_assert(V == 1 || (V == 4 && C == 1), "wide lanes are for scalar images");
   const int lane = tid & (kWave - 1);
   const int wave = uniform(tid / kWave);
   const int cx0 = x0 / g.dx;
-  const int ncx = (min(x0 + kWave * V, g.nx) - 1) / g.dx - cx0 + 4;
+  const int ncx = (min(x0 + T::width, g.nx) - 1) / g.dx - cx0 + 4;
   const int cy0 = y0 / g.dy;
-  const int ncy = (min(y0 + kFwdRows, g.ny) - 1) / g.dy - cy0 + 4;
-  const FwdStage<C, V> map = fwd_stage_map<C, V>(g, cx0, ncx, cy0, ncy, tid);
+  const int ncy = (min(y0 + T::rows, g.ny) - 1) / g.dy - cy0 + 4;
+  const FwdStage<C, T> map = fwd_stage_map<C, T>(g, cx0, ncx, cy0, ncy, tid);
 
-  const int xl = x0 + V * lane;  // the lane's first voxel
-  const int y = y0 + wave;
+  const int xl = x0 + (wave % T::strips) * kWave * V + V * lane;  // the lane's first voxel
+  const int y = y0 + wave / T::strips;
   const int yc = min(y, g.ny - 1);
   const int ty = yc / g.dy;
   const int oy = yc - ty * g.dy;
@@ -246,15 +257,15 @@ __device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float*
     const float* wx = lut_row(lut, g.dx, xc - tx * g.dx);
 #pragma unroll
     for (int l = 0; l < 4; ++l) bx[k][l] = wx[l];
-    base[k] = (ty - cy0) * fwd_pitch<C, V>() + (tx - cx0) * C;
+    base[k] = (ty - cy0) * fwd_pitch<C, T>() + (tx - cx0) * C;
   }
   auto contract = [&](const float* slot, int k) {
-    return fwd_contract<C, V>(slot, base[k], bx[k][0], bx[k][1], bx[k][2], bx[k][3], wy);
+    return fwd_contract<C, T>(slot, base[k], bx[k][0], bx[k][1], bx[k][2], bx[k][3], wy);
   };
 
   int tz = z0 / g.dz;
   int oz = z0 - tz * g.dz;
-  float r[fwd_loads<C, V>()];
+  float r[fwd_loads<C, T>()];
   // Warm-up: stage planes tz, tz+1, tz+2 one at a time (slots 0, 1, 0) and shift
   // their contractions into q0..q2; then stage plane tz+3 into slot 1 (its
   // contraction is the loop head).  One plane in flight keeps registers low.
@@ -266,8 +277,8 @@ __device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float*
 #pragma unroll 1
   for (int j = 0; j < 3; ++j) {
     __syncthreads();  // the slot may still be read (previous item or iteration)
-    fwd_fetch<C, V>(grid, g, map, tz + j, r);
-    fwd_stage<C, V>(sm.ring[j & 1], tid, r);
+    fwd_fetch<C, T>(grid, g, map, tz + j, r);
+    fwd_stage<C, T>(sm.ring[j & 1], tid, r);
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < V; ++k) {
@@ -278,8 +289,8 @@ __device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float*
     }
   }
   __syncthreads();
-  fwd_fetch<C, V>(grid, g, map, tz + 3, r);
-  fwd_stage<C, V>(sm.ring[1], tid, r);
+  fwd_fetch<C, T>(grid, g, map, tz + 3, r);
+  fwd_stage<C, T>(sm.ring[1], tid, r);
   __syncthreads();
   int slot3 = 1;  // slot holding plane tz + 3
 
@@ -289,6 +300,20 @@ __device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float*
 #pragma unroll
   for (int k = 0; k < V; ++k) all = all && active[k];
   const bool wide = V == 4 && all;
+  // Edge stores.  One voxel per lane: the wave writes the contiguous bytes of
+  // voxels [xw, xw + nw) of its row each plane.  A 64-byte segment only partly
+  // inside that span is shared with the neighbouring span (another wave,
+  // possibly another workgroup); written with non-temporal stores, its two
+  // halves reach HBM separately, which measured 50% slower overall.  The lanes
+  // that write into such a segment use ordinary stores instead, so the halves
+  // meet in L2; the other lanes stream with non-temporal stores.  m is the
+  // span's offset in its first segment; it moves by the plane size each plane.
+  constexpr int kVB = 4 * C;  // bytes per voxel
+  const int xw = x0 + (wave % T::strips) * kWave * V;
+  const int nw = max(0, min(kWave * V, g.nx - xw));
+  const int vl = xl - xw;  // this lane's first voxel within the span
+  uint32_t m = uniform((int)(reinterpret_cast<uintptr_t>(field + (((size_t)z0 * g.ny + yc) * g.nx + min(xw, g.nx - 1)) * C) & 63));
+  const uint32_t mstep = (uint32_t)((zstride * 4) & 63);
   int z = z0;
   for (;;) {
     FwdVal<C> q3[V];
@@ -297,7 +322,7 @@ __device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float*
     const int left = z1 - z;
     const bool more = g.dz - oz < left;  // another tile follows inside this range
     // its new plane tz + 4 is then at most ceil(nz/dz) + 2 = gz - 1: in bounds
-    if (more) fwd_fetch<C, V>(grid, g, map, tz + 4, r);
+    if (more) fwd_fetch<C, T>(grid, g, map, tz + 4, r);
     const int oend = more ? g.dz : oz + left;
     for (; oz < oend; ++oz, ++z) {
       const float* wz = lut_row(lut, g.dz, oz);
@@ -316,6 +341,23 @@ __device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float*
           for (int k = 0; k < V; ++k)
             if (active[k]) fwd_store<C>(out + k * C, t[k]);
         }
+      } else if constexpr (Edge) {
+        const int head = m ? (int)(64 - m + kVB - 1) / kVB : 0;     // lanes in the first partial segment
+        const int end = (int)m + kVB * nw;
+        const int tail = (end & 63) ? ((end & ~63) - (int)m) / kVB : nw;  // lanes from here on: the last one
+        if (active[0]) {
+          if (vl < head || vl >= tail) {
+            // relaxed atomic stores: plain vector stores, which the compiler
+            // does not merge with the non-temporal ones below (a plain store
+            // there would absorb the non-temporal hint of both)
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+              __hip_atomic_store(out + c, t[0][c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+          } else {
+            fwd_store<C>(out, t[0]);
+          }
+        }
+        m = (m + mstep) & 63;
       } else {
         if (active[0]) fwd_store<C>(out, t[0]);
       }
@@ -323,7 +365,7 @@ __device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float*
     }
     if (!more) break;
     // plane tz + 4 goes to the slot of plane tz + 2, consumed one tile ago
-    fwd_stage<C, V>(sm.ring[slot3 ^ 1], tid, r);
+    fwd_stage<C, T>(sm.ring[slot3 ^ 1], tid, r);
     __syncthreads();
     slot3 ^= 1;
     oz = 0;

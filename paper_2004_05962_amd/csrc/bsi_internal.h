@@ -37,8 +37,8 @@ struct FwdLaunch {
 #define BSI_FWD_BLOCKS 2048
 #endif
 constexpr int kFwdTargetBlocks = BSI_FWD_BLOCKS; // z is split until this many workgroups
-// lane_voxels: consecutive x-voxels per lane (a workgroup spans 64 lane_voxels).
-FwdLaunch make_fwd_launch(const VolGeom& g, long target = kFwdTargetBlocks, int lane_voxels = 1);
+// width x rows: the voxels and rows one workgroup covers in x and y.
+FwdLaunch make_fwd_launch(const VolGeom& g, long target = kFwdTargetBlocks, int width = kWave, int rows = kFwdRows);
 
 hipError_t launch_forward(const float* grid, float* field, const VolGeom& g, const float* lut,
                           hipStream_t s);

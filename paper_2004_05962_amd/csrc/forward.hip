@@ -11,11 +11,10 @@
 
 namespace bsi {
 
-template <int C, int V>
-__global__ __launch_bounds__(kFwdThreads) void fwd_kernel(const float* __restrict__ grid,
-                                                           float* __restrict__ field, VolGeom g,
-                                                           const float* __restrict__ lut, FwdLaunch L) {
-  __shared__ FwdSmem<C, V> sm;
+template <int C, class T, bool Edge>
+__global__ __launch_bounds__(T::threads) void fwd_kernel(const float* __restrict__ grid, float* __restrict__ field,
+                                                          VolGeom g, const float* __restrict__ lut, FwdLaunch L) {
+  __shared__ FwdSmem<C, T> sm;
   int id = xcd_remap(blockIdx.x, gridDim.x);
   const int bx = id % L.nbx;
   id /= L.nbx;
@@ -23,13 +22,21 @@ __global__ __launch_bounds__(kFwdThreads) void fwd_kernel(const float* __restric
   const int bz = id / L.nby;
   const int z0 = bz * L.zchunk;
   const int z1 = min(g.nz, z0 + L.zchunk);
-  fwd_block<C, V>(grid, field, g, lut, bx * kWave * V, by * kFwdRows, z0, z1, sm, threadIdx.x);
+  fwd_block<C, T, Edge>(grid, field, g, lut, bx * T::width, by * T::rows, z0, z1, sm, threadIdx.x);
 }
 
-FwdLaunch make_fwd_launch(const VolGeom& g, long target, int lane_voxels) {
+template <int C, class T, bool Edge>
+hipError_t launch_fwd(const float* grid, float* field, const VolGeom& g, const float* lut, hipStream_t s) {
+  const FwdLaunch L = make_fwd_launch(g, kFwdTargetBlocks, T::width, T::rows);
+  const long blocks = (long)L.nbx * L.nby * L.nbz;
+  hipLaunchKernelGGL((fwd_kernel<C, T, Edge>), dim3((unsigned)blocks), dim3(T::threads), 0, s, grid, field, g, lut, L);
+  return hipGetLastError();
+}
+
+FwdLaunch make_fwd_launch(const VolGeom& g, long target, int width, int rows) {
   FwdLaunch L;
-  L.nbx = (g.nx + kWave * lane_voxels - 1) / (kWave * lane_voxels);
-  L.nby = (g.ny + kFwdRows - 1) / kFwdRows;
+  L.nbx = (g.nx + width - 1) / width;
+  L.nby = (g.ny + rows - 1) / rows;
   // Split z (at tile boundaries) until there are >= target workgroups: enough
   // waves to keep the stores flowing, and no more (each chunk restages the 3
   // control planes before its first tile).  The split does not change the
@@ -45,32 +52,27 @@ FwdLaunch make_fwd_launch(const VolGeom& g, long target, int lane_voxels) {
   return L;
 }
 
+// Rows that start on 64-byte boundaries (every one, when nx * 12 bytes and the
+// field pointer are multiples of 64) are written whole segment by segment:
+// wider than 256 voxels, a workgroup of 2 rows x 8 strips covers 512 voxels of
+// each of its rows (0.165-0.170 ms against 0.176-0.182 for 4 x 1 at
+// 512 x 512 x 256, spacing 5).  Other rows take edge stores (fwd_block).
 hipError_t launch_forward(const float* grid, float* field, const VolGeom& g, const float* lut,
                           hipStream_t s) {
-  const FwdLaunch L = make_fwd_launch(g);
-  const long blocks = (long)L.nbx * L.nby * L.nbz;
-  hipLaunchKernelGGL((fwd_kernel<3, 1>), dim3((unsigned)blocks), dim3(kFwdThreads), 0, s, grid, field, g,
-                     lut, L);
-  return hipGetLastError();
+  const bool aligned = (g.nx * 12) % 64 == 0 && reinterpret_cast<uintptr_t>(field) % 64 == 0;
+  if (aligned && g.nx > 256) return launch_fwd<3, FwdTile<2, 8, 1>, false>(grid, field, g, lut, s);
+  if (aligned) return launch_fwd<3, FwdTileDefault, false>(grid, field, g, lut, s);
+  return launch_fwd<3, FwdTileDefault, true>(grid, field, g, lut, s);
 }
 
 hipError_t launch_forward_scalar(const float* grid, float* image, const VolGeom& g, const float* lut,
                                  hipStream_t s) {
   // Rows starting on 16-byte boundaries: 4 voxels per lane, one 16-byte store
   // each.  Otherwise one voxel per lane (4 stores per lane would each cover
-  // only every fourth dword of the wave's span).
-  if (g.nx % 4 == 0 && reinterpret_cast<uintptr_t>(image) % 16 == 0) {
-    const FwdLaunch L = make_fwd_launch(g, kFwdTargetBlocks, 4);
-    const long blocks = (long)L.nbx * L.nby * L.nbz;
-    hipLaunchKernelGGL((fwd_kernel<1, 4>), dim3((unsigned)blocks), dim3(kFwdThreads), 0, s, grid, image, g, lut,
-                       L);
-  } else {
-    const FwdLaunch L = make_fwd_launch(g);
-    const long blocks = (long)L.nbx * L.nby * L.nbz;
-    hipLaunchKernelGGL((fwd_kernel<1, 1>), dim3((unsigned)blocks), dim3(kFwdThreads), 0, s, grid, image, g, lut,
-                       L);
-  }
-  return hipGetLastError();
+  // only every fourth dword of the wave's span), with edge stores.
+  if (g.nx % 4 == 0 && reinterpret_cast<uintptr_t>(image) % 16 == 0)
+    return launch_fwd<1, FwdTile<kFwdRows, 1, 4>, false>(grid, image, g, lut, s);
+  return launch_fwd<1, FwdTileDefault, true>(grid, image, g, lut, s);
 }
 
 }  // namespace bsi

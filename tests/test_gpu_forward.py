@@ -25,6 +25,9 @@ CASES = [
     ((200, 5, 6), (1, 1, 1)),
     ((33, 17, 129), (8, 3, 6)),
     ((96, 80, 72), (3, 5, 8)),
+    ((272, 7, 9), (5, 3, 4)),         # 64-byte rows over 256 voxels: 2 rows x 8 strips, 5 strips idle
+    ((528, 3, 5), (7, 2, 2)),         # the same shape, a second workgroup in x
+    ((510, 6, 7), (5, 5, 5)),         # rows off 64-byte boundaries: edge stores on every strip
 ]
 
 
@@ -60,7 +63,7 @@ def test_forward_canary_and_rerun_bits():
 
 
 @pytest.mark.parametrize("shift", [1, 2, 3])
-@pytest.mark.parametrize("dims", [(77, 45, 31), (128, 8, 6)])
+@pytest.mark.parametrize("dims", [(77, 45, 31), (128, 8, 6), (320, 6, 5)])
 def test_forward_unaligned_field_pointer(shift, dims):
     """A field that starts 4, 8 or 12 bytes past a 16-byte boundary: the same
     bits as an aligned field, and nothing written outside it."""
