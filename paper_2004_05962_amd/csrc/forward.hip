@@ -53,14 +53,11 @@ FwdLaunch make_fwd_launch(const VolGeom& g, long target, int width, int rows) {
 }
 
 // Rows that start on 64-byte boundaries (every one, when nx * 12 bytes and the
-// field pointer are multiples of 64) are written whole segment by segment:
-// wider than 256 voxels, a workgroup of 2 rows x 8 strips covers 512 voxels of
-// each of its rows (0.165-0.170 ms against 0.176-0.182 for 4 x 1 at
-// 512 x 512 x 256, spacing 5).  Other rows take edge stores (fwd_block).
+// field pointer are multiples of 64) are written whole segment by segment;
+// other rows take edge stores (fwd_block).
 hipError_t launch_forward(const float* grid, float* field, const VolGeom& g, const float* lut,
                           hipStream_t s) {
   const bool aligned = (g.nx * 12) % 64 == 0 && reinterpret_cast<uintptr_t>(field) % 64 == 0;
-  if (aligned && g.nx > 256) return launch_fwd<3, FwdTile<2, 8, 1>, false>(grid, field, g, lut, s);
   if (aligned) return launch_fwd<3, FwdTileDefault, false>(grid, field, g, lut, s);
   return launch_fwd<3, FwdTileDefault, true>(grid, field, g, lut, s);
 }

@@ -25,8 +25,8 @@ CASES = [
     ((200, 5, 6), (1, 1, 1)),
     ((33, 17, 129), (8, 3, 6)),
     ((96, 80, 72), (3, 5, 8)),
-    ((272, 7, 9), (5, 3, 4)),         # 64-byte rows over 256 voxels: 2 rows x 8 strips, 5 strips idle
-    ((528, 3, 5), (7, 2, 2)),         # the same shape, a second workgroup in x
+    ((272, 7, 9), (5, 3, 4)),         # rows of 64-byte multiples, ragged strips and rows
+    ((528, 3, 5), (7, 2, 2)),         # the same, nine strips
     ((510, 6, 7), (5, 5, 5)),         # rows off 64-byte boundaries: edge stores on every strip
 ]
 
