@@ -215,6 +215,26 @@ __device__ __forceinline__ void fwd_store(float* p, const float (&t)[C]) {
 }
 
 typedef float fwd_f4 __attribute__((ext_vector_type(4)));
+typedef float fwd_f3 __attribute__((ext_vector_type(3)));
+
+// Buffer stores (edge stores below): resource word 3 for raw 32-bit access on
+// CDNA3/4, and the non-temporal cache-policy bit.
+constexpr int kBufferFlags = 0x00020000;
+constexpr int kCpolNT = 2;
+template <int C>
+__device__ __forceinline__ void fwd_buffer_store(__amdgpu_buffer_rsrc_t rs, int off, const float (&t)[C], int cpol);
+template <>
+__device__ __forceinline__ void fwd_buffer_store<3>(__amdgpu_buffer_rsrc_t rs, int off, const float (&t)[3],
+                                                    int cpol) {
+  if (cpol) __builtin_amdgcn_raw_buffer_store_b96(fwd_f3{t[0], t[1], t[2]}, rs, off, 0, kCpolNT);
+  else __builtin_amdgcn_raw_buffer_store_b96(fwd_f3{t[0], t[1], t[2]}, rs, off, 0, 0);
+}
+template <>
+__device__ __forceinline__ void fwd_buffer_store<1>(__amdgpu_buffer_rsrc_t rs, int off, const float (&t)[1],
+                                                    int cpol) {
+  if (cpol) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, t[0]), rs, off, 0, kCpolNT);
+  else __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, t[0]), rs, off, 0, 0);
+}
 
 // Collective over the workgroup (T::threads threads, all bounds uniform).
 // C = 3 for displacement grids, C = 1 for scalar images.  x0, y0: the
@@ -308,12 +328,17 @@ __device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float*
   // that write into such a segment use ordinary stores instead, so the halves
   // meet in L2; the other lanes stream with non-temporal stores.  m is the
   // span's offset in its first segment; it moves by the plane size each plane.
+  // Both kinds are buffer stores over the wave's row (a global store of each
+  // kind on the two sides of a branch would be merged by the compiler into one
+  // ordinary store); the row is under 4 GB, so byte offsets fit 32 bits.
   constexpr int kVB = 4 * C;  // bytes per voxel
   const int xw = x0 + (wave % T::strips) * kWave * V;
   const int nw = max(0, min(kWave * V, g.nx - xw));
   const int vl = xl - xw;  // this lane's first voxel within the span
   uint32_t m = uniform((int)(reinterpret_cast<uintptr_t>(field + (((size_t)z0 * g.ny + yc) * g.nx + min(xw, g.nx - 1)) * C) & 63));
   const uint32_t mstep = (uint32_t)((zstride * 4) & 63);
+  float* row = field + ((size_t)z0 * g.ny + yc) * g.nx * C;  // the wave's row in plane z
+  const int lane_off = min(xl, g.nx - 1) * kVB;
   int z = z0;
   for (;;) {
     FwdVal<C> q3[V];
@@ -345,19 +370,15 @@ __device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float*
         const int head = m ? (int)(64 - m + kVB - 1) / kVB : 0;     // lanes in the first partial segment
         const int end = (int)m + kVB * nw;
         const int tail = (end & 63) ? ((end & ~63) - (int)m) / kVB : nw;  // lanes from here on: the last one
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(row, 0, g.nx * kVB, kBufferFlags);
         if (active[0]) {
-          if (vl < head || vl >= tail) {
-            // relaxed atomic stores: plain vector stores, which the compiler
-            // does not merge with the non-temporal ones below (a plain store
-            // there would absorb the non-temporal hint of both)
-#pragma unroll
-            for (int c = 0; c < C; ++c)
-              __hip_atomic_store(out + c, t[0][c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-          } else {
-            fwd_store<C>(out, t[0]);
-          }
+          if (vl < head || vl >= tail)
+            fwd_buffer_store<C>(rs, lane_off, t[0], 0);
+          else
+            fwd_buffer_store<C>(rs, lane_off, t[0], kCpolNT);
         }
         m = (m + mstep) & 63;
+        row += zstride;
       } else {
         if (active[0]) fwd_store<C>(out, t[0]);
       }
