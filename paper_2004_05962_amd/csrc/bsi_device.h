@@ -236,6 +236,55 @@ __device__ __forceinline__ void fwd_buffer_store<1>(__amdgpu_buffer_rsrc_t rs, i
   else __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, t[0]), rs, off, 0, 0);
 }
 
+// Edge stores for a wave that writes one voxel per lane of a contiguous row
+// span, voxels [xw, xw + nw) of its row, once per plane.  A 64-byte segment
+// only partly inside that span is shared with the neighbouring span (another
+// wave, possibly another workgroup); written with non-temporal stores, its two
+// halves reach HBM separately, which measured 50% slower overall.  The lanes
+// that write into such a segment use ordinary stores instead, so the halves
+// meet in L2; the other lanes stream with non-temporal stores.  m is the span's
+// offset in its first segment; it moves by the plane size each plane.  Both
+// kinds are buffer stores over the wave's row (a global store of each kind on
+// the two sides of a branch would be merged by the compiler into one ordinary
+// store); a row is under 4 GB, so byte offsets fit 32 bits.
+template <int C>
+struct FwdEdgeStore {
+  static constexpr int kVB = 4 * C;  // bytes per voxel
+  float* row;                        // the wave's row in the current plane
+  size_t zstride;                    // floats per plane
+  uint32_t m, mstep;
+  int row_bytes, nw, vl, lane_off;
+
+  // field: the volume; (z0, yc): the wave's first plane and its row; xw: the
+  // span's first voxel; x: this lane's voxel (clamped into the row by the caller
+  // when idle).
+  __device__ __forceinline__ FwdEdgeStore(float* field, const VolGeom& g, int z0, int yc, int xw, int x) {
+    zstride = (size_t)g.ny * g.nx * C;
+    row = field + ((size_t)z0 * g.ny + yc) * g.nx * C;
+    row_bytes = g.nx * kVB;
+    nw = max(0, min(kWave, g.nx - xw));
+    vl = x - xw;
+    lane_off = x * kVB;
+    m = (uint32_t)uniform((int)(reinterpret_cast<uintptr_t>(row + (size_t)min(xw, g.nx - 1) * C) & 63));
+    mstep = (uint32_t)((zstride * 4) & 63);
+  }
+  // Store this lane's voxel of the current plane (if active), then step to the next plane.
+  __device__ __forceinline__ void store(bool active, const float (&t)[C]) {
+    const int head = m ? (int)(64 - m + kVB - 1) / kVB : 0;               // lanes in the first partial segment
+    const int end = (int)m + kVB * nw;
+    const int tail = (end & 63) ? ((end & ~63) - (int)m) / kVB : nw;     // lanes from here on: the last one
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(row, 0, row_bytes, kBufferFlags);
+    if (active) {
+      if (vl < head || vl >= tail)
+        fwd_buffer_store<C>(rs, lane_off, t, 0);
+      else
+        fwd_buffer_store<C>(rs, lane_off, t, kCpolNT);
+    }
+    m = (m + mstep) & 63;
+    row += zstride;
+  }
+};
+
 // Collective over the workgroup (T::threads threads, all bounds uniform).
 // C = 3 for displacement grids, C = 1 for scalar images.  x0, y0: the
 // workgroup's first voxel and row.  The lane of strip k owns the V consecutive
@@ -244,13 +293,14 @@ __device__ __forceinline__ void fwd_buffer_store<1>(__amdgpu_buffer_rsrc_t rs, i
 // every row to start on a 16-byte boundary: a lane whose 4 voxels all lie in
 // the volume writes them with one 16-byte store.  Edge (V = 1): lanes whose
 // voxel lies in a 64-byte segment shared with the neighbouring span use
-// ordinary stores (see below); for rows that do not start on 64-byte boundaries.
+// ordinary stores (FwdEdgeStore); for rows that do not start on 64-byte boundaries.
 template <int C, class T = FwdTileDefault, bool Edge = false>
 __device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float* __restrict__ field,
                                           const VolGeom& g, const float* __restrict__ lut, int x0, int y0,
                                           int z0, int z1, FwdSmem<C, T>& sm, int tid) {
   constexpr int V = T::lane_voxels;
   static_assert(V == 1 || (V == 4 && C == 1), "wide lanes are for scalar images");
+  static_assert(!Edge || V == 1, "edge stores assume one voxel per lane");
   const int lane = tid & (kWave - 1);
   const int wave = uniform(tid / kWave);
   const int cx0 = x0 / g.dx;
@@ -320,25 +370,8 @@ __device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float*
 #pragma unroll
   for (int k = 0; k < V; ++k) all = all && active[k];
   const bool wide = V == 4 && all;
-  // Edge stores.  One voxel per lane: the wave writes the contiguous bytes of
-  // voxels [xw, xw + nw) of its row each plane.  A 64-byte segment only partly
-  // inside that span is shared with the neighbouring span (another wave,
-  // possibly another workgroup); written with non-temporal stores, its two
-  // halves reach HBM separately, which measured 50% slower overall.  The lanes
-  // that write into such a segment use ordinary stores instead, so the halves
-  // meet in L2; the other lanes stream with non-temporal stores.  m is the
-  // span's offset in its first segment; it moves by the plane size each plane.
-  // Both kinds are buffer stores over the wave's row (a global store of each
-  // kind on the two sides of a branch would be merged by the compiler into one
-  // ordinary store); the row is under 4 GB, so byte offsets fit 32 bits.
-  constexpr int kVB = 4 * C;  // bytes per voxel
-  const int xw = x0 + (wave % T::strips) * kWave * V;
-  const int nw = max(0, min(kWave * V, g.nx - xw));
-  const int vl = xl - xw;  // this lane's first voxel within the span
-  uint32_t m = uniform((int)(reinterpret_cast<uintptr_t>(field + (((size_t)z0 * g.ny + yc) * g.nx + min(xw, g.nx - 1)) * C) & 63));
-  const uint32_t mstep = (uint32_t)((zstride * 4) & 63);
-  float* row = field + ((size_t)z0 * g.ny + yc) * g.nx * C;  // the wave's row in plane z
-  const int lane_off = min(xl, g.nx - 1) * kVB;
+  // (edge stores: one voxel per lane, so the wave's span is its strip)
+  FwdEdgeStore<C> edge(field, g, z0, yc, x0 + (wave % T::strips) * kWave * V, min(xl, g.nx - 1));
   int z = z0;
   for (;;) {
     FwdVal<C> q3[V];
@@ -367,18 +400,7 @@ __device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float*
             if (active[k]) fwd_store<C>(out + k * C, t[k]);
         }
       } else if constexpr (Edge) {
-        const int head = m ? (int)(64 - m + kVB - 1) / kVB : 0;     // lanes in the first partial segment
-        const int end = (int)m + kVB * nw;
-        const int tail = (end & 63) ? ((end & ~63) - (int)m) / kVB : nw;  // lanes from here on: the last one
-        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(row, 0, g.nx * kVB, kBufferFlags);
-        if (active[0]) {
-          if (vl < head || vl >= tail)
-            fwd_buffer_store<C>(rs, lane_off, t[0], 0);
-          else
-            fwd_buffer_store<C>(rs, lane_off, t[0], kCpolNT);
-        }
-        m = (m + mstep) & 63;
-        row += zstride;
+        edge.store(active[0], t[0]);
       } else {
         if (active[0]) fwd_store<C>(out, t[0]);
       }

@@ -52,6 +52,8 @@ struct GenFwdSmem {
   int zt[kGenMaxZ];       // their window start floor(t_z)
 };
 
+// Edge: rows off 64-byte boundaries, written with edge stores (FwdEdgeStore).
+template <bool Edge>
 __global__ __launch_bounds__(kFwdThreads) void gen_fwd_kernel(const float* __restrict__ grid,
                                                                float* __restrict__ field, VolGeom g, GenGeom q,
                                                                int nbx, int nby, int zchunk) {
@@ -115,6 +117,7 @@ __global__ __launch_bounds__(kFwdThreads) void gen_fwd_kernel(const float* __res
 
   const size_t zstride = (size_t)g.ny * g.nx * 3;
   float* out = field + (((size_t)z0 * g.ny + yc) * g.nx + xc) * 3;
+  FwdEdgeStore<3> edge(field, g, z0, yc, x0, xc);
   int z = z0;
   for (;;) {
     const FwdVal<3> q3 = fwd_contract<3>(sm.f.ring[slot3], base, bx[0], bx[1], bx[2], bx[3], wy);
@@ -129,7 +132,8 @@ __global__ __launch_bounds__(kFwdThreads) void gen_fwd_kernel(const float* __res
 #pragma unroll
       for (int c = 0; c < 3; ++c)
         t[c] = fmaf(wz[3], q3.v[c], fmaf(wz[2], q2.v[c], fmaf(wz[1], q1.v[c], wz[0] * q0.v[c])));
-      if (active) fwd_store<3>(out, t);
+      if constexpr (Edge) edge.store(active, t);
+      else if (active) fwd_store<3>(out, t);
     }
     if (!more) break;
     fwd_stage<3>(sm.f.ring[slot3 ^ 1], tid, r);
@@ -344,8 +348,13 @@ hipError_t launch_forward_general(const float* grid, float* field, const VolGeom
   chunks = std::max(1, std::min(chunks, g.nz));
   const int zchunk = (g.nz + chunks - 1) / chunks;
   const int nbz = (g.nz + zchunk - 1) / zchunk;
-  hipLaunchKernelGGL(gen_fwd_kernel, dim3((unsigned)(base * nbz)), dim3(kFwdThreads), 0, s, grid, field, g, q,
-                     nbx, nby, zchunk);
+  // rows on 64-byte boundaries: non-temporal stores; otherwise edge stores
+  if ((g.nx * 12) % 64 == 0 && reinterpret_cast<uintptr_t>(field) % 64 == 0)
+    hipLaunchKernelGGL(gen_fwd_kernel<false>, dim3((unsigned)(base * nbz)), dim3(kFwdThreads), 0, s, grid, field,
+                       g, q, nbx, nby, zchunk);
+  else
+    hipLaunchKernelGGL(gen_fwd_kernel<true>, dim3((unsigned)(base * nbz)), dim3(kFwdThreads), 0, s, grid, field,
+                       g, q, nbx, nby, zchunk);
   return hipGetLastError();
 }
 

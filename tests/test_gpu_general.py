@@ -20,6 +20,7 @@ CASES = [
     ((130, 9, 11), (1.0, 2.2, 3.3), (0.0, -1.1, -0.2)),      # unit spacing in x, several strips
     ((70, 45, 20), (63.5, 7.75, 10.0), (-63.0, -2.5, -9.5)),  # very coarse x
     ((20, 20, 20), (4.0, 4.0, 4.0), (0.0, 0.0, 0.0)),         # integer and aligned
+    ((192, 9, 7), (5.5, 2.0, 3.0), (-1.0, 0.0, -0.5)),        # rows of 64-byte multiples, 3 strips
 ]
 
 
@@ -69,6 +70,25 @@ def test_general_adjoint_identity_and_rerun_bits():
     scale = float((bx.double() * y.double()).abs().sum())
     assert abs(lhs - rhs) <= 1e-5 * scale
     assert torch.equal(bty, _adjoint(y, dims, spacing, origin))
+
+
+@pytest.mark.parametrize("shift", [1, 3])
+def test_general_forward_unaligned_output_same_bits(shift):
+    # rows of 64-byte multiples written through a pointer 4 or 12 bytes past a
+    # 64-byte boundary: the edge-store path, same bits as the aligned path
+    dims, spacing, origin = (192, 9, 7), (5.5, 2.0, 3.0), (-1.0, 0.0, -0.5)
+    say("general forward, unaligned output", dims, shift)
+    grid = dev(_grid(dims, spacing, origin, seed=9))
+    aligned = torch.empty(bsi.field_shape(dims), device="cuda")
+    bsi.bsi_forward_general(grid, dims, spacing, origin, aligned)
+    n = aligned.numel()
+    buf = torch.full((n + 32,), 1.0e30, device="cuda")
+    out = buf[shift:shift + n].view(bsi.field_shape(dims))
+    assert out.data_ptr() % 64 == 4 * shift
+    bsi.bsi_forward_general(grid, dims, spacing, origin, out)
+    torch.cuda.synchronize()
+    assert torch.equal(out, aligned)
+    assert bool((buf[:shift] == 1.0e30).all()) and bool((buf[shift + n:] == 1.0e30).all())
 
 
 def test_general_integer_case_agrees_with_aligned_kernels():
