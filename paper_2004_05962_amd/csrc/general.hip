@@ -218,6 +218,7 @@ constexpr int kGxRows = 4;                 // rows per workgroup, one per wave
 constexpr int kGxThreads = kGxRows * kWave;
 constexpr int kGxTiles = kWave;            // tiles per wave
 constexpr int kGxOut = kGxTiles - 3;       // outputs per wave
+constexpr int kGxChunk = 6;                // voxels loaded together per lane
 
 __global__ __launch_bounds__(kGxThreads) void gen_gather_x_kernel(const float* __restrict__ in,
                                                                    float* __restrict__ out, GenAxis a,
@@ -238,14 +239,28 @@ __global__ __launch_bounds__(kGxThreads) void gen_gather_x_kernel(const float* _
   if (t >= 0 && t < a.g - 3) {  // tiles 0 .. g-4 hold voxels
     const float* src = in + (size_t)row * a.n * 3;
     const int v1 = first[t + 1];
-    for (int v = first[t]; v < v1; ++v) {
-      const F3 d = ldf3(src + (size_t)v * 3);
-      const float* pw = w + 4 * v;
+    // a chunk's loads are all issued before its sums (clamped addresses, valid
+    // voxels summed in ascending order): several loads in flight per lane
+    for (int v0 = first[t]; v0 < v1; v0 += kGxChunk) {
+      F3 d[kGxChunk];
+      float b[kGxChunk][4];
 #pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        mm[3 * l] = fmaf(pw[l], d.x, mm[3 * l]);
-        mm[3 * l + 1] = fmaf(pw[l], d.y, mm[3 * l + 1]);
-        mm[3 * l + 2] = fmaf(pw[l], d.z, mm[3 * l + 2]);
+      for (int j = 0; j < kGxChunk; ++j) {
+        const int v = min(v0 + j, v1 - 1);
+        d[j] = ldf3(src + (size_t)v * 3);
+#pragma unroll
+        for (int l = 0; l < 4; ++l) b[j][l] = w[4 * v + l];
+      }
+#pragma unroll
+      for (int j = 0; j < kGxChunk; ++j) {
+        if (v0 + j < v1) {
+#pragma unroll
+          for (int l = 0; l < 4; ++l) {
+            mm[3 * l] = fmaf(b[j][l], d[j].x, mm[3 * l]);
+            mm[3 * l + 1] = fmaf(b[j][l], d[j].y, mm[3 * l + 1]);
+            mm[3 * l + 2] = fmaf(b[j][l], d[j].z, mm[3 * l + 2]);
+          }
+        }
       }
     }
   }
