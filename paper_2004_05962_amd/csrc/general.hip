@@ -157,12 +157,15 @@ __global__ __launch_bounds__(256) void gen_table_kernel(GenAxis a, int* __restri
   for (int l = 0; l < 4; ++l) w[4 * v + l] = b[l];
 }
 
+constexpr int kGatherChunk = 8;  // voxels loaded together per output
+
 // One separable gather along an axis.  The input is viewed as [outer][n][inner]
 // F3 values (n along the axis), the output as [outer][g][inner]; output
 // (o, c, k) sums the inputs (o, v, k) whose window holds c, v ascending.
 __global__ __launch_bounds__(256) void gen_gather_kernel(const float* __restrict__ in, float* __restrict__ out,
                                                           GenAxis a, const int* __restrict__ tile,
-                                                          const float* __restrict__ w, long outer, int inner) {
+                                                          const int* __restrict__ first, const float* __restrict__ w,
+                                                          long outer, int inner) {
   const long id = (long)blockIdx.x * 256 + threadIdx.x;
   const long total = outer * a.g * (long)inner;
   if (id >= total) return;
@@ -170,21 +173,31 @@ __global__ __launch_bounds__(256) void gen_gather_kernel(const float* __restrict
   const long rest = id / inner;
   const int c = (int)(rest % a.g);
   const long o = rest / a.g;
-  // first voxel whose window can hold c: t >= c - 3, i.e. v >= (c - 3) s + o;
-  // start one below the estimate and skip voxels whose window ends before c
-  int v = (int)floor((double)(c - 3) * a.s + a.o) - 1;
-  if (v < 0) v = 0;
+  // the voxels whose window holds c: c - 3 <= i(v) <= c, i.e. [first[c-3], first[c+1])
+  const int va = first[max(c - 3, 0)], vb = first[c + 1];
   float sx = 0.f, sy = 0.f, sz = 0.f;
   const float* src = in + ((size_t)o * a.n * inner + k) * 3;
-  for (; v < a.n; ++v) {
-    const int i = tile[v];
-    if (i > c) break;        // windows only move right
-    if (i < c - 3) continue;
-    const float b = w[4 * v + (c - i)];
-    const float* p = src + (size_t)v * inner * 3;
-    sx = fmaf(b, p[0], sx);
-    sy = fmaf(b, p[1], sy);
-    sz = fmaf(b, p[2], sz);
+  // a chunk's loads are all issued before its sums (clamped indices, valid
+  // voxels summed in ascending order)
+  for (int v0 = va; v0 < vb; v0 += kGatherChunk) {
+    int vi[kGatherChunk];
+#pragma unroll
+    for (int j = 0; j < kGatherChunk; ++j) vi[j] = min(v0 + j, vb - 1);
+    float b[kGatherChunk];
+    F3 d[kGatherChunk];
+#pragma unroll
+    for (int j = 0; j < kGatherChunk; ++j) {
+      b[j] = w[4 * vi[j] + (c - tile[vi[j]])];
+      d[j] = ldf3(src + (size_t)vi[j] * inner * 3);
+    }
+#pragma unroll
+    for (int j = 0; j < kGatherChunk; ++j) {
+      if (v0 + j < vb) {
+        sx = fmaf(b[j], d[j].x, sx);
+        sy = fmaf(b[j], d[j].y, sy);
+        sz = fmaf(b[j], d[j].z, sz);
+      }
+    }
   }
   float* dst = out + (((size_t)o * a.g + c) * inner + k) * 3;
   dst[0] = sx;
@@ -192,7 +205,7 @@ __global__ __launch_bounds__(256) void gen_gather_kernel(const float* __restrict
   dst[2] = sz;
 }
 
-// First voxel of every x tile: first[t] = min{v : i(v) >= t} for t = 0..g
+// First voxel of every tile of an axis: first[t] = min{v : i(v) >= t} for t = 0..g
 // (first[g] = n), from the nondecreasing table of window starts.
 __global__ __launch_bounds__(256) void gen_first_kernel(GenAxis a, const int* __restrict__ tile,
                                                          int* __restrict__ first) {
@@ -290,7 +303,7 @@ constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 struct GenWork {
   int* tile[3];
   float* w[3];
-  int* first;  // first voxel of every x tile (gx + 1 entries)
+  int* first[3];  // first voxel of every tile, per axis (g + 1 entries)
   float* A;   // [nz][ny][gx][3]
   float* Bm;  // [nz][gy][gx][3]
 };
@@ -305,8 +318,10 @@ size_t gen_layout(const GenGeom& q, void* base, GenWork* wk) {
     if (wk) wk->w[i] = reinterpret_cast<float*>(p + off);
     off += align256((size_t)ax[i]->n * 4 * sizeof(float));
   }
-  if (wk) wk->first = reinterpret_cast<int*>(p + off);
-  off += align256((size_t)(q.x.g + 1) * sizeof(int));
+  for (int i = 0; i < 3; ++i) {
+    if (wk) wk->first[i] = reinterpret_cast<int*>(p + off);
+    off += align256((size_t)(ax[i]->g + 1) * sizeof(int));
+  }
   if (wk) wk->A = reinterpret_cast<float*>(p + off);
   off += align256((size_t)q.z.n * q.y.n * q.x.g * 3 * sizeof(float));
   if (wk) wk->Bm = reinterpret_cast<float*>(p + off);
@@ -384,27 +399,28 @@ hipError_t launch_adjoint_general(const float* dfield, float* grad, const GenGeo
     hipLaunchKernelGGL(gen_table_kernel, dim3(blocks_for(ax[i]->n)), dim3(256), 0, s, *ax[i], wk.tile[i], wk.w[i]);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(gen_first_kernel, dim3(blocks_for(ax[i]->g + 1)), dim3(256), 0, s, *ax[i], wk.tile[i],
+                       wk.first[i]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   // x: [nz*ny][nx] -> A [nz*ny][gx] by tile moments: kGxRows rows and kGxOut
   // outputs per workgroup
-  hipLaunchKernelGGL(gen_first_kernel, dim3(blocks_for(q.x.g + 1)), dim3(256), 0, s, q.x, wk.tile[0], wk.first);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e;
   const long rows = (long)q.z.n * q.y.n;
   const long nseg = (q.x.g + kGxOut - 1) / kGxOut;
   const long blocks = (rows + kGxRows - 1) / kGxRows * nseg;
   if (blocks > 0x7fffffffL) return hipErrorInvalidValue;
   hipLaunchKernelGGL(gen_gather_x_kernel, dim3((unsigned)blocks), dim3(kGxThreads), 0, s, dfield, wk.A, q.x,
-                     wk.first, wk.w[0], rows);
+                     wk.first[0], wk.w[0], rows);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   // y: [nz][ny][gx] -> Bm [nz][gy][gx]
   hipLaunchKernelGGL(gen_gather_kernel, dim3(blocks_for((long)q.z.n * q.y.g * q.x.g)), dim3(256), 0, s, wk.A,
-                     wk.Bm, q.y, wk.tile[1], wk.w[1], (long)q.z.n, q.x.g);
+                     wk.Bm, q.y, wk.tile[1], wk.first[1], wk.w[1], (long)q.z.n, q.x.g);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // z: [1][nz][gy*gx] -> grad [gz][gy*gx]
   hipLaunchKernelGGL(gen_gather_kernel, dim3(blocks_for((long)q.z.g * q.y.g * q.x.g)), dim3(256), 0, s, wk.Bm,
-                     grad, q.z, wk.tile[2], wk.w[2], 1L, q.y.g * q.x.g);
+                     grad, q.z, wk.tile[2], wk.first[2], wk.w[2], 1L, q.y.g * q.x.g);
   return hipGetLastError();
 }
 
