@@ -245,11 +245,19 @@ __device__ __forceinline__ void adj_plane_offsets(const AdjBrick& b, int nx, int
   }
 }
 
+// Streaming load of one voxel of dfield: non-temporal, since every voxel is
+// read once.  The read stream then does not leave the caches full of dfield
+// lines that the following kernel's writes have to displace (measured: the
+// next forward 0.180 -> 0.171 ms, pass 1 itself a few percent faster).
+__device__ __forceinline__ F3 ldf3_stream(const float* p) {
+  return F3{__builtin_nontemporal_load(p), __builtin_nontemporal_load(p + 1), __builtin_nontemporal_load(p + 2)};
+}
+
 template <int DX>
 __device__ __forceinline__ void adj_plane_load(const float* __restrict__ plane, const uint32_t (&off)[DX],
                                                F3 (&d)[DX]) {
 #pragma unroll
-  for (int k = 0; k < DX; ++k) d[k] = ldf3(plane + off[k]);
+  for (int k = 0; k < DX; ++k) d[k] = ldf3_stream(plane + off[k]);
 }
 
 // Stage a loaded plane in the wave's LDS region (lanes exchange data: tile rows
@@ -294,7 +302,7 @@ __device__ __forceinline__ void adj_xmoments_generic(const float* __restrict__ r
   for (int o0 = 0; o0 < nval; o0 += kAdjChunk) {
     F3 d[kAdjChunk];
 #pragma unroll
-    for (int j = 0; j < kAdjChunk; ++j) d[j] = o0 + j < nval ? ldf3(row + 3 * (o0 + j)) : F3{0.f, 0.f, 0.f};
+    for (int j = 0; j < kAdjChunk; ++j) d[j] = o0 + j < nval ? ldf3_stream(row + 3 * (o0 + j)) : F3{0.f, 0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < kAdjChunk; ++j)
       if (o0 + j < nval) adj_xmoment_step(o0 + j, lutx + 4 * (o0 + j), d[j], M);
