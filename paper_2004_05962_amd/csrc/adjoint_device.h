@@ -249,15 +249,19 @@ __device__ __forceinline__ void adj_plane_offsets(const AdjBrick& b, int nx, int
 // read once.  The read stream then does not leave the caches full of dfield
 // lines that the following kernel's writes have to displace (measured: the
 // next forward 0.180 -> 0.171 ms, pass 1 itself a few percent faster).
-__device__ __forceinline__ F3 ldf3_stream(const float* p) {
-  return F3{__builtin_nontemporal_load(p), __builtin_nontemporal_load(p + 1), __builtin_nontemporal_load(p + 2)};
+template <bool Stream>
+__device__ __forceinline__ F3 ldf3_dfield(const float* p) {
+  if constexpr (Stream)
+    return F3{__builtin_nontemporal_load(p), __builtin_nontemporal_load(p + 1), __builtin_nontemporal_load(p + 2)};
+  else
+    return ldf3(p);
 }
 
-template <int DX>
+template <int DX, bool Stream>
 __device__ __forceinline__ void adj_plane_load(const float* __restrict__ plane, const uint32_t (&off)[DX],
                                                F3 (&d)[DX]) {
 #pragma unroll
-  for (int k = 0; k < DX; ++k) d[k] = ldf3_stream(plane + off[k]);
+  for (int k = 0; k < DX; ++k) d[k] = ldf3_dfield<Stream>(plane + off[k]);
 }
 
 // Stage a loaded plane in the wave's LDS region (lanes exchange data: tile rows
@@ -295,6 +299,7 @@ __device__ __forceinline__ void adj_plane_moments(const float* __restrict__ buf,
 }
 
 
+template <bool Stream>
 __device__ __forceinline__ void adj_xmoments_generic(const float* __restrict__ row, int nval,
                                                      const float* __restrict__ lutx, F3 (&M)[4]) {
 #pragma unroll
@@ -302,7 +307,7 @@ __device__ __forceinline__ void adj_xmoments_generic(const float* __restrict__ r
   for (int o0 = 0; o0 < nval; o0 += kAdjChunk) {
     F3 d[kAdjChunk];
 #pragma unroll
-    for (int j = 0; j < kAdjChunk; ++j) d[j] = o0 + j < nval ? ldf3_stream(row + 3 * (o0 + j)) : F3{0.f, 0.f, 0.f};
+    for (int j = 0; j < kAdjChunk; ++j) d[j] = o0 + j < nval ? ldf3_dfield<Stream>(row + 3 * (o0 + j)) : F3{0.f, 0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < kAdjChunk; ++j)
       if (o0 + j < nval) adj_xmoment_step(o0 + j, lutx + 4 * (o0 + j), d[j], M);
@@ -337,7 +342,8 @@ __device__ __forceinline__ void adj_tables(const AdjGeom& a, const AdjBrick& b, 
 }
 
 // Pass 1 for one brick.  Collective over the workgroup (kAdjThreads threads).
-template <int DX>
+// Stream: dfield is read with non-temporal loads.
+template <int DX, bool Stream = true>
 __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, float* __restrict__ part,
                                           const AdjGeom& a, const float* __restrict__ lut, int brick,
                                           AdjSmem<DX>& sm, int tid) {
@@ -408,10 +414,10 @@ __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, floa
     F3 d[DX];
     uint32_t off[DX];
     adj_plane_offsets<DX>(b, g.nx, ywave, lane, off);
-    adj_plane_load<DX>(plane0, off, d);
+    adj_plane_load<DX, Stream>(plane0, off, d);
     for (int z = b.z0; z < b.ze; ++z) {
       adj_plane_stage<DX>(wbuf, lane, d);
-      if (z + 1 < b.ze) adj_plane_load<DX>(plane0 + (size_t)(z + 1 - b.z0) * zs, off, d);
+      if (z + 1 < b.ze) adj_plane_load<DX, Stream>(plane0 + (size_t)(z + 1 - b.z0) * zs, off, d);
       F3 M[4];
       adj_plane_moments<DX>(wbuf, lane, nval, lutx, M);
       step(M, z);
@@ -419,7 +425,7 @@ __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, floa
   } else {
     for (int z = b.z0; z < b.ze; ++z) {
       F3 M[4];
-      adj_xmoments_generic(src, nval, lutx, M);
+      adj_xmoments_generic<Stream>(src, nval, lutx, M);
       src += zs;
       step(M, z);
     }
