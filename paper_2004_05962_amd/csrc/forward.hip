@@ -53,11 +53,17 @@ FwdLaunch make_fwd_launch(const VolGeom& g, long target, int width, int rows) {
 }
 
 // Rows that start on 64-byte boundaries (every one, when nx * 12 bytes and the
-// field pointer are multiples of 64) are written whole segment by segment;
-// other rows take edge stores (fwd_block).
+// field pointer are multiples of 64) are written whole segment by segment.
+// Wider than 256 voxels and with z-tiles of at least 5 planes, a workgroup of
+// 2 rows x 8 strips covers 512 voxels of each of its rows (at 512 x 512 x 256,
+// spacing 5: 167 against 172 us inside the forward + adjoint step).  Its 16
+// waves meet at one barrier per z-tile, which cost more than it gained at
+// spacing 3 (0.224 against 0.189 ms).  Other rows take edge stores (fwd_block).
 hipError_t launch_forward(const float* grid, float* field, const VolGeom& g, const float* lut,
                           hipStream_t s) {
   const bool aligned = (g.nx * 12) % 64 == 0 && reinterpret_cast<uintptr_t>(field) % 64 == 0;
+  if (aligned && g.nx > 256 && g.dz >= 5)
+    return launch_fwd<3, FwdTile<2, 8, 1>, false>(grid, field, g, lut, s);
   if (aligned) return launch_fwd<3, FwdTileDefault, false>(grid, field, g, lut, s);
   return launch_fwd<3, FwdTileDefault, true>(grid, field, g, lut, s);
 }

@@ -25,8 +25,9 @@ CASES = [
     ((200, 5, 6), (1, 1, 1)),
     ((33, 17, 129), (8, 3, 6)),
     ((96, 80, 72), (3, 5, 8)),
-    ((272, 7, 9), (5, 3, 4)),         # rows of 64-byte multiples, ragged strips and rows
-    ((528, 3, 5), (7, 2, 2)),         # the same, nine strips
+    ((272, 7, 9), (5, 3, 4)),         # rows of 64-byte multiples, ragged strips and rows (4 x 1)
+    ((272, 7, 12), (5, 3, 5)),        # the same with 5-plane z-tiles: 2 rows x 8 strips, 5 strips idle
+    ((528, 3, 13), (7, 2, 6)),        # 2 x 8, a second workgroup in x
     ((510, 6, 7), (5, 5, 5)),         # rows off 64-byte boundaries: edge stores on every strip
 ]
 
