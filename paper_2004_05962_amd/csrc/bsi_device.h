@@ -294,7 +294,8 @@ struct FwdEdgeStore {
 // the volume writes them with one 16-byte store.  Edge (V = 1): lanes whose
 // voxel lies in a 64-byte segment shared with the neighbouring span use
 // ordinary stores (FwdEdgeStore); for rows that do not start on 64-byte boundaries.
-template <int C, class T = FwdTileDefault, bool Edge = false>
+// Plain (V = 1, no Edge): ordinary stores for every voxel.
+template <int C, class T = FwdTileDefault, bool Edge = false, bool Plain = false>
 __device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float* __restrict__ field,
                                           const VolGeom& g, const float* __restrict__ lut, int x0, int y0,
                                           int z0, int z1, FwdSmem<C, T>& sm, int tid) {
@@ -401,6 +402,11 @@ __device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float*
         }
       } else if constexpr (Edge) {
         edge.store(active[0], t[0]);
+      } else if constexpr (Plain) {
+        if (active[0]) {
+#pragma unroll
+          for (int c = 0; c < C; ++c) out[c] = t[0][c];
+        }
       } else {
         if (active[0]) fwd_store<C>(out, t[0]);
       }
