@@ -371,7 +371,8 @@ __device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float*
 #pragma unroll
   for (int k = 0; k < V; ++k) all = all && active[k];
   const bool wide = V == 4 && all;
-  // (edge stores: one voxel per lane, so the wave's span is its strip)
+  // Used by the Edge path only (elsewhere the compiler drops it).  One voxel per
+  // lane, so the wave's span is its strip.
   FwdEdgeStore<C> edge(field, g, z0, yc, x0 + (wave % T::strips) * kWave * V, min(xl, g.nx - 1));
   int z = z0;
   for (;;) {
