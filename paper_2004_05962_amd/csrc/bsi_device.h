@@ -246,7 +246,8 @@ __device__ __forceinline__ void fwd_buffer_store<1>(__amdgpu_buffer_rsrc_t rs, i
 // offset in its first segment; it moves by the plane size each plane.  Both
 // kinds are buffer stores over the wave's row (a global store of each kind on
 // the two sides of a branch would be merged by the compiler into one ordinary
-// store); a row is under 4 GB, so byte offsets fit 32 bits.
+// store); a row holds at most 2^20 voxels (the ABI's axis limit), so its byte
+// offsets fit 32 bits.
 template <int C>
 struct FwdEdgeStore {
   static constexpr int kVB = 4 * C;  // bytes per voxel
