@@ -13,7 +13,8 @@ Printed as ONE JSON line on stdout (logs go to stderr), with:
                 traffic measured by rocprofv3 counters when the committed
                 measurement matches the current kernel sources;
   cpu_baseline  the FP64 oracle (forward + adjoint) on the first 128 z-planes of
-                the same volume, on the host's cores;
+                the same volume, and its adjoint at 256^3, on the host's cores
+                (medians of 3 runs);
   extras        forward at spacings 3 and 8, the adjoint alone at 256^3
                 (MALL flushed between repetitions), the 32-volume batched
                 graph launch against per-volume launches, and one SSD
@@ -112,36 +113,44 @@ def cpu_info():
     return model, len(os.sched_getaffinity(0))
 
 
-def cpu_baseline(grid_np, dfield_np, dims, spacing, planes=128, planes_1t=16):
-    """FP64 oracle, forward + adjoint, on the first `planes` z-planes with all
-    the host's threads, and its forward on the first `planes_1t` planes with one."""
+def cpu_baseline(grid_np, dfield_np, dims, spacing, cfg3, planes=128, planes_1t=16, reps=3):
+    """FP64 oracle on the host's cores: forward (triple sum, OpenMP over z) and
+    adjoint (per-control-point gather, OpenMP over control points) on the first
+    `planes` z-planes of the benchmark volume, the median of `reps` runs each;
+    the adjoint alone on the 256^3 workload (median of `reps`); and the forward
+    on `planes_1t` planes with one thread."""
     import oracle
     d = spacing[2]
 
     def sub(p):
         return (dims[0], dims[1], p), grid_np[:-(-p // d) + 3], dfield_np[:p]
 
+    def timed(fn, *args):
+        t0 = time.perf_counter()
+        fn(*args)
+        return time.perf_counter() - t0
+
     sub_dims, g, y = sub(planes)
-    t0 = time.perf_counter()
-    oracle.forward(g, sub_dims, spacing)
-    t1 = time.perf_counter()
-    oracle.adjoint(y, sub_dims, spacing)
-    t2 = time.perf_counter()
+    t_fwd = median([timed(oracle.forward, g, sub_dims, spacing) for _ in range(reps)])
+    t_adj = median([timed(oracle.adjoint_gather, y, sub_dims, spacing) for _ in range(reps)])
+    c3_dims, c3_sp = cfg3["dims"], cfg3["spacing"]
+    t_c3 = median([timed(oracle.adjoint_gather, cfg3["dfield"], c3_dims, c3_sp) for _ in range(reps)])
     threads = oracle.num_threads()
     dims1, g1, _ = sub(planes_1t)
     oracle.set_num_threads(1)
-    t3 = time.perf_counter()
-    oracle.forward(g1, dims1, spacing)
-    t4 = time.perf_counter()
+    t_1t = timed(oracle.forward, g1, dims1, spacing)
     oracle.set_num_threads(threads)
     vox = dims[0] * dims[1] * planes
     vox1 = dims[0] * dims[1] * planes_1t
+    vox3 = c3_dims[0] * c3_dims[1] * c3_dims[2]
     model, affinity = cpu_info()
-    return {"value": vox / (t2 - t0) / 1e9, "unit": "GVoxel/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {planes} of {dims[2]} z-planes ({vox / 1e6:.1f} M voxels), forward {t1 - t0:.2f} s "
-                      f"(OpenMP) + adjoint {t2 - t1:.2f} s (serial scatter), FP64",
-            "forward_gvoxel_s": vox / (t1 - t0) / 1e9, "adjoint_gvoxel_s": vox / (t2 - t1) / 1e9,
-            "forward_1_thread_gvoxel_s": vox1 / (t4 - t3) / 1e9, "cpu_model": model, "affinity_cpus": affinity}
+    return {"value": vox / (t_fwd + t_adj) / 1e9, "unit": "GVoxel/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {planes} of {dims[2]} z-planes ({vox / 1e6:.1f} M voxels): forward {t_fwd:.2f} s "
+                      f"(triple sum) + adjoint {t_adj:.2f} s (per-point gather), FP64, {threads} OpenMP threads, "
+                      f"median of {reps}",
+            "forward_gvoxel_s": vox / t_fwd / 1e9, "adjoint_gvoxel_s": vox / t_adj / 1e9,
+            "adjoint_256cubed_d5_gvoxel_s": vox3 / t_c3 / 1e9,
+            "forward_1_thread_gvoxel_s": vox1 / t_1t / 1e9, "cpu_model": model, "affinity_cpus": affinity}
 
 
 def main():
@@ -262,7 +271,7 @@ def main():
     cpu = None
     if not args.quick and not args.no_cpu and rank == 0:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(case["grid"], dfield_np, dims, spacing)
+        cpu = cpu_baseline(case["grid"], dfield_np, dims, spacing, workloads.cfg3())
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "GVoxel/s", "n_gpus": 1, "steps": args.steps,

@@ -156,4 +156,14 @@ def adjoint_points(dfield, dims, spacing, cps) -> np.ndarray:
     return out
 
 
+def adjoint_gather(dfield, dims, spacing) -> np.ndarray:
+    """Transpose of Eq. 1 by the per-control-point gather (``adjoint_points`` over
+    every control point, spread over OpenMP threads): the same sums as ``adjoint``
+    in another order; FP64 gradient of shape (gz, gy, gx, 3)."""
+    gx, gy, gz = grid_dims(dims, spacing)
+    cz, cy, cx = np.meshgrid(np.arange(gz), np.arange(gy), np.arange(gx), indexing="ij")
+    cps = np.stack([cx.ravel(), cy.ravel(), cz.ravel()], axis=1)
+    return adjoint_points(dfield, dims, spacing, cps).reshape(gz, gy, gx, 3)
+
+
 from . import brute, general, warp, registration, scalar  # noqa: E402,F401

@@ -171,18 +171,24 @@ int oracle_adjoint(const double* dfield, const int32_t dims[3], const int32_t sp
 /* One entry of the adjoint, computed as a gather: control point a = (ax,ay,az)
    collects every voxel whose 4x4x4 window contains it, i.e. floor(x/dx) in
    [ax-3, ax] (and likewise in y, z), each weighted by the basis product for
-   index l = ax - floor(x/dx).  Used to check single points of large volumes. */
+   index l = ax - floor(x/dx).  Each point is an independent literal sum over
+   its support in raster order, so the points are spread over OpenMP threads;
+   used for single points of large volumes and, over every point, as the
+   parallel form of the whole adjoint. */
 int oracle_adjoint_points(const double* dfield, const int32_t dims[3], const int32_t spacing[3],
                           const int64_t* cps, int64_t count, double* out) {
     if (check_geometry(dims, spacing)) return -1;
-    const int64_t nx = dims[0], ny = dims[1], nz = dims[2];
+    const int64_t nx = dims[0], ny = dims[1];
     const int64_t g[3] = {grid_points(dims[0], spacing[0]), grid_points(dims[1], spacing[1]),
                           grid_points(dims[2], spacing[2])};
+    for (int64_t p = 0; p < count; ++p)
+        for (int ax = 0; ax < 3; ++ax)
+            if (cps[3 * p + ax] < 0 || cps[3 * p + ax] >= g[ax]) return -2;
+#pragma omp parallel for schedule(dynamic, 64)
     for (int64_t p = 0; p < count; ++p) {
         const int64_t a[3] = {cps[3 * p], cps[3 * p + 1], cps[3 * p + 2]};
         int64_t lo[3], hi[3];
         for (int ax = 0; ax < 3; ++ax) {
-            if (a[ax] < 0 || a[ax] >= g[ax]) return -2;
             lo[ax] = (a[ax] - 3) * spacing[ax];
             if (lo[ax] < 0) lo[ax] = 0;
             hi[ax] = (a[ax] + 1) * spacing[ax];
@@ -206,7 +212,6 @@ int oracle_adjoint_points(const double* dfield, const int32_t dims[3], const int
                     s[1] += wt * d[1];
                     s[2] += wt * d[2];
                 }
-        (void)nz;
         out[3 * p] = s[0];
         out[3 * p + 1] = s[1];
         out[3 * p + 2] = s[2];

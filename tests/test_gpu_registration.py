@@ -4,7 +4,11 @@
 Warp / SSD bar: the oracle forms the sample coordinate x + T in FP32, as the
 kernel does, so both take the same cell decisions; the rest is FP64.  Values
 within 1e-5 of the image range, loss within 1e-5 relative.  Loop bar: the loss
-of every step within 1e-3 relative of the FP64 trajectory."""
+of every step within 1e-3 relative of the FP64 trajectory (at 48 x 40 x 32
+computed in the test, at 256 x 256 x 160 from the oracle's stored run)."""
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -17,6 +21,9 @@ from oracle import registration as oreg
 from oracle import warp as owarp
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN_TRAJ = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "registration_256x256x160_d5_trajectory.json")
 
 
 def _pair(dims, nblobs, seed=1004, sigma=2.0):
@@ -85,8 +92,15 @@ def test_registration_full_size_loss_falls_and_resume_is_exact():
     L0_ref, g0_ref = oreg.step(np.zeros(case["grid_true"].shape), moving, fixed, spacing)
     reg.eta = 0.5 / float(np.abs(g0_ref).max())
     loss0 = reg.evaluate(loss_out=torch.empty(1, device="cuda"))
-    assert abs(float(host(loss0)[0]) - L0_ref) <= 1e-3 * L0_ref
-    assert max_abs(host(reg.grad), g0_ref) <= 1e-3 * float(np.abs(g0_ref).max())
+    assert abs(float(host(loss0)[0]) - L0_ref) <= 1e-5 * L0_ref
+    # the fused step's bar: its T is summed in another order than the oracle's,
+    # so a sample coordinate within rounding of a cell boundary may change cell
+    # (the trilinear gradient jumps there by the image's second difference)
+    diff = np.abs(host(reg.grad) - g0_ref)
+    gmax = float(np.abs(g0_ref).max())
+    print(f"registration first gradient: max err {diff.max():.3e} mean err {diff.mean():.3e} max |g| {gmax:.3e}")
+    assert diff.max() <= 1e-4 * gmax
+    assert diff.mean() <= 1e-6 * gmax
 
     say("registration 256x256x160 50 steps with resume at 25")
     reg.run(25)
@@ -99,3 +113,22 @@ def test_registration_full_size_loss_falls_and_resume_is_exact():
     other.load_state_dict(state)
     other.run(25)
     assert torch.equal(other.grid, reg.grid)
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_registration_full_size_trajectory_matches_oracle(fused):
+    """50 descent steps at 256 x 256 x 160 against the FP64 oracle's trajectory
+    (stored by tests/golden/make_registration_trajectory.py, which calls only the
+    oracle): every step's loss within 1e-3 relative."""
+    with open(GOLDEN_TRAJ) as f:
+        gold = json.load(f)
+    dims = tuple(gold["dims"])
+    case, moving = _pair(dims, nblobs=200)
+    say("registration 256x256x160 trajectory", "fused" if fused else "unfused")
+    reg = bsi.SSDRegistration(dev(case["fixed"]), dev(moving), case["spacing"], fused=fused)
+    reg.eta = gold["eta"]
+    losses = host(reg.run(gold["steps"]))
+    ref = np.array(gold["losses"])
+    rel = np.abs(losses - ref) / ref
+    print(f"trajectory ({'fused' if fused else 'unfused'}): max rel loss err {rel.max():.3e}")
+    assert rel.max() <= 1e-3, rel.max()
