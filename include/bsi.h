@@ -49,8 +49,10 @@ extern "C" {
 #define BSI_OK 0
 #define BSI_ERR_INVALID_ARG (-1) /* null pointer, n < 1, d < 1, bad size     */
 #define BSI_ERR_UNSUPPORTED (-2) /* d > BSI_MAX_SPACING, or a size too large
-                                    (an axis above BSI_MAX_DIM, or a voxel plane
-                                    nx * ny of 2^32 / 3 voxels or more)      */
+                                    (an axis above BSI_MAX_DIM, a voxel plane
+                                    nx * ny of 2^32 / 3 voxels or more, or a
+                                    control plane gx * gy of 2^31 / 3 points
+                                    or more)                                 */
 #define BSI_ERR_HIP (-3)         /* a HIP call failed; see bsi_last_error()  */
 #define BSI_ERR_NO_DEVICE (-4)   /* no HIP device is visible                 */
 #define BSI_ERR_NOMEM (-5)       /* allocation of a batched plan failed      */
@@ -243,9 +245,12 @@ typedef struct bsi_batch bsi_batch;
 int32_t bsi_batch_create(int32_t count, const int32_t* dims3xN, const int32_t* spacing3xN,
                          bsi_batch** out);
 
-/* Bind device buffers (host arrays of `count` device pointers each).  grids and
-   fields are used by the forward, dfields and grid_grads by the adjoint; pass
-   NULL for a whole pass to leave it out.  Invalidates a captured graph. */
+/* Bind device buffers (host arrays of exactly `count` device pointers each;
+   the library cannot check their length or the buffers' sizes, which must be
+   those of each volume's grid and field).  grids and fields are used by the
+   forward, dfields and grid_grads by the adjoint; pass NULL for a whole pass to
+   leave it out.  Synchronises the plan's device first (a launch still running
+   reads the tables this call rewrites), then invalidates a captured graph. */
 int32_t bsi_batch_bind(bsi_batch* plan, const float* const* grids, float* const* fields,
                        const float* const* dfields, float* const* grid_grads);
 
@@ -253,8 +258,10 @@ int32_t bsi_batch_bind(bsi_batch* plan, const float* const* grids, float* const*
    with the bound buffers (the outputs are written while timing) and keep the
    fastest.  Drops a captured graph.  The choice is stored in the JSON file
    named by the environment variable BSI_TUNE_CACHE (if set) and read back by
-   later plans with the same geometry.  BSI_FORCE_CONFIG=<index> skips timing.
-   Synchronises `stream`.  Schedules never change result bits. */
+   later plans with the same geometry.  BSI_FORCE_CONFIG=<index> skips timing;
+   an index that is not a valid schedule is rejected with INVALID_ARG (here and
+   in bsi_batch_create).  Synchronises the plan's device.  Schedules never
+   change result bits. */
 int32_t bsi_batch_tune(bsi_batch* plan, hipStream_t stream);
 
 /* Index of the schedule the plan uses, and the number of candidates. */
@@ -268,7 +275,9 @@ int32_t bsi_batch_run(bsi_batch* plan, hipStream_t stream);
 int32_t bsi_batch_run_separate(bsi_batch* plan, hipStream_t stream);
 
 /* Capture bsi_batch_run into a HIP graph (stream capture on `stream`) and
-   instantiate it.  Errors: INVALID_ARG (nothing bound), HIP. */
+   instantiate it, replacing an earlier graph (the plan's device is synchronised
+   first, so no launch of that graph is still running).
+   Errors: INVALID_ARG (nothing bound), HIP. */
 int32_t bsi_batch_capture(bsi_batch* plan, hipStream_t stream);
 
 /* Replay the captured graph with one hipGraphLaunch on `stream`.

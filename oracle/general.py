@@ -13,10 +13,13 @@ for the general case, per axis:
   g = floor((n - 1 - o) / s) + 4 points per axis.
 
 For integer s and o = 0 this is exactly the aligned case: t = x/s, g = ceil(n/s) + 3.
-t is formed in FP64 as (x - o) / s from the FP32 values of s and o (the
-precision in which the library takes its decisions).  Forward: the plain triple
-sum; adjoint: the raster-order scatter of the same products.
+s and o are the FP32 values the library receives; t is their exact rational
+(x - o)/s, so the window start i = floor(t) is the exact one, and u = t - i is
+rounded to FP64 once.  Forward: the plain triple sum; adjoint: the raster-order
+scatter of the same products.
 """
+from fractions import Fraction
+
 import numpy as np
 
 from . import basis
@@ -26,26 +29,32 @@ def _f(v):
     return float(np.float32(v))
 
 
+def _t(x, s, o):
+    """t = (x - o)/s as an exact rational (s, o already FP32 values)."""
+    return (Fraction(int(x)) - Fraction(o)) / Fraction(s)
+
+
 def axis_table(n, s, o):
     """Window start i and weights B(u) (n, 4) of every coordinate 0..n-1."""
     s, o = _f(s), _f(o)
     i = np.empty(n, np.int64)
     w = np.empty((n, 4), np.float64)
     for x in range(n):
-        t = (float(x) - o) / s
-        i[x] = int(np.floor(t))
-        w[x] = basis(t - i[x])
+        t = _t(x, s, o)
+        i[x] = t.numerator // t.denominator
+        w[x] = basis(float(t - int(i[x])))
     return i, w
 
 
 def grid_dims(dims, spacing, origin):
-    """Control points per axis (gx, gy, gz)."""
+    """Control points per axis (gx, gy, gz): floor((n - 1 - o)/s) + 4."""
     out = []
     for n, s, o in zip(dims, spacing, origin):
         s, o = _f(s), _f(o)
         if not (s >= 1.0 and -s < o <= 0.0):
             raise ValueError("need spacing >= 1 and -spacing < origin <= 0")
-        out.append(int(np.floor((float(n) - 1.0 - o) / s)) + 4)
+        t = _t(int(n) - 1, s, o)
+        out.append(t.numerator // t.denominator + 4)
     return tuple(out)
 
 

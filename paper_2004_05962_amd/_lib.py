@@ -310,8 +310,8 @@ def bsi_ssd_grad(field, moving, fixed, dims, dfield, loss, workspace, stream=Non
     x = _ptr(fixed, "fixed", (nz, ny, nx))
     d = _ptr(dfield, "dfield", field_shape(dims))
     l = _ptr(loss, "loss", (1,))
-    nbytes = workspace.numel() * workspace.element_size()
-    _check(lib().bsi_ssd_grad(f, m, x, _triple(dims, "dims"), d, l, _raw(workspace), nbytes, _stream(stream)))
+    w, nbytes = _workspace(workspace)
+    _check(lib().bsi_ssd_grad(f, m, x, _triple(dims, "dims"), d, l, w, nbytes, _stream(stream)))
 
 
 def bsi_ssd_fused_workspace_size(dims, spacing):
@@ -340,12 +340,20 @@ def bsi_descent_step(grid, grad, eta, stream=None):
 
 
 # --------------------------------------------------------------------- batched
-def _ptr_array(tensors, name):
+# Geometry of every live plan (keyed by its handle), so that bind can check each
+# bound tensor against its volume before the library stores the pointers.
+_PLANS = {}
+
+
+def _ptr_array(tensors, name, shapes):
     if tensors is None:
         return None
+    tensors = list(tensors)
+    if len(tensors) != len(shapes):
+        raise ValueError(f"{name} holds {len(tensors)} tensors; the plan has {len(shapes)} volumes")
     arr = (_VP * len(tensors))()
-    for i, t in enumerate(tensors):
-        arr[i] = _ptr(t, f"{name}[{i}]").value
+    for i, (t, shape) in enumerate(zip(tensors, shapes)):
+        arr[i] = _ptr(t, f"{name}[{i}]", shape).value
     return arr
 
 
@@ -353,16 +361,28 @@ def bsi_batch_create(dims_list, spacing_list):
     n = len(dims_list)
     if n != len(spacing_list) or n < 1:
         raise ValueError("need one spacing per volume and at least one volume")
-    d = (ctypes.c_int32 * (3 * n))(*[int(v) for t in dims_list for v in t])
-    s = (ctypes.c_int32 * (3 * n))(*[int(v) for t in spacing_list for v in t])
+    dims = [tuple(int(v) for v in t) for t in dims_list]
+    spacing = [tuple(int(v) for v in t) for t in spacing_list]
+    if any(len(t) != 3 for t in dims + spacing):
+        raise ValueError("every dims and spacing entry must have three values")
+    d = (ctypes.c_int32 * (3 * n))(*[v for t in dims for v in t])
+    s = (ctypes.c_int32 * (3 * n))(*[v for t in spacing for v in t])
     plan = _VP()
     _check(lib().bsi_batch_create(n, d, s, ctypes.byref(plan)))
+    _PLANS[plan.value] = (dims, spacing)
     return plan
 
 
 def bsi_batch_bind(plan, grids=None, fields=None, dfields=None, grid_grads=None):
-    arrs = [_ptr_array(grids, "grids"), _ptr_array(fields, "fields"), _ptr_array(dfields, "dfields"),
-            _ptr_array(grid_grads, "grid_grads")]
+    """Bind per-volume buffers; each list must hold exactly one tensor per volume, of
+    that volume's grid or field shape (checked here, before the library sees them)."""
+    if plan is None or not plan.value or plan.value not in _PLANS:
+        raise ValueError("not a live batched plan")
+    dims, spacing = _PLANS[plan.value]
+    gshapes = [grid_shape(d, s) for d, s in zip(dims, spacing)]
+    fshapes = [field_shape(d) for d in dims]
+    arrs = [_ptr_array(grids, "grids", gshapes), _ptr_array(fields, "fields", fshapes),
+            _ptr_array(dfields, "dfields", fshapes), _ptr_array(grid_grads, "grid_grads", gshapes)]
     _check(lib().bsi_batch_bind(plan, *arrs))
 
 
@@ -394,4 +414,5 @@ def bsi_batch_launch(plan, stream=None):
 
 def bsi_batch_destroy(plan):
     if plan:
+        _PLANS.pop(plan.value, None)
         lib().bsi_batch_destroy(plan)

@@ -20,6 +20,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libbsi.so")
+# host-only checker of the kernels' index arithmetic (CPU tests), linked to libbsi
+CHECK_LIB = os.path.join(HERE, "libbsi_check.so")
+CHECK_SRC = "index_check.cpp"
 OBJDIR = os.path.join(ROOT, "_build", "obj")
 
 SOURCES = ["lut.hip", "forward.hip", "lerp.hip", "adjoint.hip", "warp.hip", "fused.hip", "general.hip", "batch.hip", "abi.cpp"]
@@ -61,7 +64,21 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stderr)
     os.replace(tmp, LIB)
+    build_checker()
     return LIB
+
+
+def build_checker() -> str:
+    """Compile the host-side index checker against the freshly linked libbsi.so."""
+    tmp = CHECK_LIB + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, "-x", "hip"] + CFLAGS + ["-shared", os.path.join(CSRC, CHECK_SRC), "-L" + HERE, "-lbsi",
+                                           "-Wl,-rpath,$ORIGIN", "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        noise = [l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l and l.strip()]
+        raise RuntimeError("index checker build failed:\n" + "\n".join(noise))
+    os.replace(tmp, CHECK_LIB)
+    return CHECK_LIB
 
 
 if __name__ == "__main__":

@@ -38,6 +38,16 @@ int32_t current_device(int* dev) {
   return BSI_OK;
 }
 
+// Offsets within one control plane (gx * gy points of 3 floats) are signed
+// 32-bit in the kernels' staging maps, with -1 for "outside the window".
+int32_t check_control_plane(int32_t gx, int32_t gy) {
+  if ((double)gx * gy * 3 >= 2147483648.0) {
+    set_error("a control plane (gx * gy) of 7.16e8 points or more");
+    return BSI_ERR_UNSUPPORTED;
+  }
+  return BSI_OK;
+}
+
 int32_t make_geom(const int32_t dims[3], const int32_t spacing[3], VolGeom* g) {
   if (!dims || !spacing) {
     set_error("dims and spacing must be non-null");
@@ -78,7 +88,7 @@ int32_t make_geom(const int32_t dims[3], const int32_t spacing[3], VolGeom* g) {
     set_error("a voxel plane (nx * ny) above 1.43e9 voxels");
     return BSI_ERR_UNSUPPORTED;
   }
-  return BSI_OK;
+  return check_control_plane(g->gx, g->gy);
 }
 
 }  // namespace bsi

@@ -31,13 +31,17 @@ __global__ __launch_bounds__(kGatherThreads) void adj_pass2_kernel(const float* 
 }
 
 namespace {
-AdjAxis make_axis(int n, int d, int u, int nb) {
+// k units of u voxels per brick.
+AdjAxis make_axis(int n, int d, int u, int k) {
   AdjAxis a;
   a.u = u;
   a.U = (n + u - 1) / u;
-  a.nb = nb;
-  const int umax = (a.U + nb - 1) / nb;  // units in the largest brick
-  a.cm = (umax * u - 1) / d + 5;
+  a.k = k < a.U ? k : a.U;
+  a.nb = (a.U + a.k - 1) / a.k;
+  a.w = a.k * u;
+  // a brick of k whole tiles meets k + 3 control points; a brick of rows that
+  // may start inside a tile meets at most (w - 1)/d + 2 tiles, plus 3
+  a.cm = u == d ? a.k + 3 : (a.w - 1) / d + 5;
   return a;
 }
 }  // namespace
@@ -45,35 +49,15 @@ AdjAxis make_axis(int n, int d, int u, int nb) {
 AdjGeom make_adj_geom(const VolGeom& g) {
   AdjGeom a;
   a.g = g;
-  // x: whole tiles, at most kAdjTilesX per brick
-  const int Ux = (g.nx + g.dx - 1) / g.dx;
-  a.x = make_axis(g.nx, g.dx, g.dx, (Ux + kAdjTilesX - 1) / kAdjTilesX);
-  // y: whole tiles (single rows when a tile is taller than kAdjMaxY), <= kAdjMaxY rows per brick
+  // x: kAdjTilesX whole tiles per brick (one per lane of a row)
+  a.x = make_axis(g.nx, g.dx, g.dx, kAdjTilesX);
+  // y: whole tiles (single rows when a tile is taller than kAdjMaxY), at most
+  // kAdjMaxY rows per brick
   const int uy = g.dy <= kAdjMaxY ? g.dy : 1;
-  const int Uy = (g.ny + uy - 1) / uy;
-  const int my = kAdjMaxY / uy;
-  a.y = make_axis(g.ny, g.dy, uy, (Uy + my - 1) / my);
-  // z: whole tiles; about kAdjTargetZ voxels deep, or the count in
-  // [ceil(Uz/6), ceil(Uz/2)] that best fills whole rounds of kAdjSlots
-  const int Uz = (g.nz + g.dz - 1) / g.dz;
-  const int mz = kAdjTargetZ / g.dz > 0 ? kAdjTargetZ / g.dz : 1;
-  const long base = (long)a.x.nb * a.y.nb;
-  int nbz = (Uz + mz - 1) / mz;
-  const int lo = (Uz + 5) / 6 > 0 ? (Uz + 5) / 6 : 1;
-  const int hi = (Uz + 1) / 2 > 0 ? (Uz + 1) / 2 : 1;
-  if (base * hi >= kAdjSlots) {
-    double best = -1.0;
-    for (int c = lo; c <= hi; ++c) {
-      const long tot = base * c;
-      const long rounds = (tot + kAdjSlots - 1) / kAdjSlots;
-      const double eff = (double)tot / (double)(rounds * kAdjSlots);
-      if (eff > best + 1e-9) {
-        best = eff;
-        nbz = c;
-      }
-    }
-  }
-  a.z = make_axis(g.nz, g.dz, g.dz, nbz);
+  a.y = make_axis(g.ny, g.dy, uy, kAdjMaxY / uy);
+  // z: whole tiles, about kAdjTargetZ voxels deep (at least one tile)
+  const int kz = kAdjTargetZ / g.dz > 0 ? kAdjTargetZ / g.dz : 1;
+  a.z = make_axis(g.nz, g.dz, g.dz, kz);
   return a;
 }
 

@@ -1,10 +1,10 @@
 // Adjoint of Eq. 1 (its transpose), as a deterministic two-pass gather.
 //
-// Pass 1 (one workgroup per brick).  Each axis is cut into whole tiles (rows
-// instead when a y-tile is taller than a brick), spread evenly over the bricks:
-// at most kAdjTilesX x-tiles and kAdjMaxY rows per brick; the z split fills
-// whole rounds of resident workgroups.  A workgroup reads its brick's dfield exactly
-// once.  Each thread owns one x-tile of one row (lane = x-tile, 16 tiles x 4
+// Pass 1 (one workgroup per brick).  Each axis is cut into bricks of a fixed
+// number of whole tiles (rows instead when a y-tile is taller than a brick),
+// the last brick holding the rest: kAdjTilesX x-tiles, at most kAdjMaxY rows
+// and about kAdjTargetZ planes per brick.  A workgroup reads its brick's dfield
+// exactly once.  Each thread owns one x-tile of one row (lane = x-tile, 16 tiles x 4
 // rows per wave) and marches along z.  At every voxel plane it loads the tile
 // row's dx voxels (contiguous) and forms the four x-moments
 //   M_l = sum_o Bx_l(o) * dfield[z][y][tx*dx + o]          (l = 0..3)
@@ -44,17 +44,22 @@ constexpr int kAdjTilesX = BSI_ADJ_TILES_X;        // x-tiles per brick (= lanes
 constexpr int kAdjThreads = 512;
 constexpr int kAdjMaxY = kAdjThreads / kAdjTilesX;  // rows per brick
 constexpr int kAdjMaxCx = kAdjTilesX + 4;           // window bound in x
-// Workgroups of pass 1 resident at once on MI355X (256 CUs x 2).  The z split
-// is chosen so the brick count fills whole rounds of these slots; it is a
-// constant of the library, not a property queried from the device, so the
-// decomposition (and the bits) never depend on the GPU it runs on.
-constexpr int kAdjSlots = 512;
+// The decomposition is a function of the geometry and these constants only,
+// never of the device, so the bits never depend on the GPU it runs on.
 #ifndef BSI_ADJ_TARGET_Z
 #define BSI_ADJ_TARGET_Z 24
 #endif
 constexpr int kAdjTargetZ = BSI_ADJ_TARGET_Z;       // brick depth bound (voxels)
 constexpr int kAdjMaxDX = 12;                       // largest specialised x spacing
 constexpr int kAdjChunk = 4;                        // generic path: voxels per step
+// Voxel planes of loads in flight per wave.  Two cost 3 DX more VGPRs per
+// lane: up to DX = 7 that stays within 128 (two 512-thread workgroups per CU,
+// as many as the LDS allows); from DX = 8 the LDS admits one workgroup per CU,
+// which leaves 256 VGPRs per lane.
+#ifndef BSI_ADJ_PREFETCH_MAX_DX
+#define BSI_ADJ_PREFETCH_MAX_DX 12
+#endif
+__host__ __device__ constexpr int adj_prefetch(int dx) { return dx <= BSI_ADJ_PREFETCH_MAX_DX ? 2 : 1; }
 static_assert(kWave % kAdjTilesX == 0, "a wave holds whole rows of tiles");
 
 constexpr int kAdjWaves = kAdjThreads / kWave;
@@ -91,7 +96,7 @@ struct AdjBrick {
   int ntx;                     // x-tiles of the brick inside the volume
 };
 
-__device__ __forceinline__ AdjBrick adj_brick_geom(const AdjGeom& a, int brick) {
+__host__ __device__ inline AdjBrick adj_brick_geom(const AdjGeom& a, int brick) {
   const VolGeom& g = a.g;
   AdjBrick b;
   const int bx = brick % a.x.nb;
@@ -111,6 +116,20 @@ __device__ __forceinline__ AdjBrick adj_brick_geom(const AdjGeom& a, int brick) 
   b.Cy = (b.ye - 1) / g.dy - b.cy0 + 4;
   b.ntx = (b.xe - 1) / g.dx - b.cx0 + 1;
   return b;
+}
+
+// Control planes of a brick's window: the z-tiles of its voxels plus 3.
+__host__ __device__ inline int adj_brick_cz(const AdjGeom& a, const AdjBrick& b) {
+  return (b.ze - 1) / a.g.dz - b.cz0 + 4;
+}
+
+// Floats per brick in the workspace, and the offset of window point
+// (czl, cyl, cxl) within its brick's partials.
+__host__ __device__ inline size_t adj_brick_stride(const AdjGeom& a) {
+  return (size_t)a.z.cm * a.y.cm * a.x.cm * 3;
+}
+__host__ __device__ inline size_t adj_part_offset(const AdjGeom& a, int czl, int cyl, int cxl) {
+  return ((size_t)(czl * a.y.cm + cyl) * a.x.cm + cxl) * 3;
 }
 
 // Finished control plane number k of the brick (czl = cz - cz0).  Collective:
@@ -163,7 +182,7 @@ __device__ __forceinline__ void adj_emit(const AdjGeom& a, const AdjBrick& b, fl
       az = fmaf(wv, q[2], az);
     }
     const int cz_l = czl - (k - kk);
-    stf3(pbase + ((size_t)(cz_l * a.y.cm + cyl) * a.x.cm + cxl) * 3, F3{ax, ay, az});
+    stf3(pbase + adj_part_offset(a, cz_l, cyl, cxl), F3{ax, ay, az});
   }
 }
 
@@ -227,7 +246,7 @@ __device__ __forceinline__ void adj_xmoment_step(int o, const float* __restrict_
 // v = row * kAdjTilesX * DX + x; lane j loads v = k * 64 + j (k < DX), i.e.
 // consecutive lanes read consecutive 12-byte voxels.
 template <int DX>
-__device__ __forceinline__ void adj_plane_offsets(const AdjBrick& b, int nx, int ywave, int lane,
+__host__ __device__ inline void adj_plane_offsets(const AdjBrick& b, int nx, int ywave, int lane,
                                                   uint32_t (&off)[DX]) {
   // Every lane loads from a valid address, clamped into the brick, with no
   // branch or select around the load (the data is only consumed one plane
@@ -240,7 +259,7 @@ __device__ __forceinline__ void adj_plane_offsets(const AdjBrick& b, int nx, int
     const int v = k * kWave + lane;
     const int r = v / (kAdjTilesX * DX);
     const int xl = v - r * (kAdjTilesX * DX);
-    const int x = min(b.x0 + xl, b.xe - 1), y = min(ywave + r, b.ye - 1);
+    const int x = imin(b.x0 + xl, b.xe - 1), y = imin(ywave + r, b.ye - 1);
     off[k] = ((uint32_t)y * (uint32_t)nx + (uint32_t)x) * 3u;  // a plane holds < 2^32 floats (make_geom)
   }
 }
@@ -350,7 +369,7 @@ __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, floa
   const VolGeom& g = a.g;
   const int dx = DX > 0 ? DX : g.dx;
   const AdjBrick b = adj_brick_geom(a, brick);
-  float* pbase = part + (size_t)brick * a.z.cm * a.y.cm * a.x.cm * 3;
+  float* pbase = part + (size_t)brick * adj_brick_stride(a);
 
   adj_tables(a, b, lut, sm.e, tid);
   // (the first y-contraction's barrier orders these writes before any read)
@@ -407,20 +426,35 @@ __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, floa
   };
 
   if constexpr (DX > 0) {
-    // Per plane: wait for its loads (issued one plane earlier), stage them in
-    // LDS, which frees the registers, issue the next plane's loads into them,
-    // then read back this lane's tile row and reduce it.  One plane of loads is
-    // always in flight while the previous one is reduced (and emitted).
-    F3 d[DX];
+    // Per plane: wait for its loads (issued kAhead planes earlier), stage them
+    // in LDS, which frees their registers, issue the loads of the plane kAhead
+    // ahead into them, then read back this lane's tile row and reduce it.
+    // kAhead planes of loads are in flight while a plane is reduced (and
+    // emitted).  With two, the loop is unrolled by two so that
+    // each register set keeps fixed names.
     uint32_t off[DX];
     adj_plane_offsets<DX>(b, g.nx, ywave, lane, off);
-    adj_plane_load<DX, Stream>(plane0, off, d);
-    for (int z = b.z0; z < b.ze; ++z) {
+    auto plane = [&](int z) { return plane0 + (size_t)(z - b.z0) * zs; };
+    constexpr int kAhead = adj_prefetch(DX);
+    auto consume = [&](F3 (&d)[DX], int z) {
       adj_plane_stage<DX>(wbuf, lane, d);
-      if (z + 1 < b.ze) adj_plane_load<DX, Stream>(plane0 + (size_t)(z + 1 - b.z0) * zs, off, d);
+      if (z + kAhead < b.ze) adj_plane_load<DX, Stream>(plane(z + kAhead), off, d);
       F3 M[4];
       adj_plane_moments<DX>(wbuf, lane, nval, lutx, M);
       step(M, z);
+    };
+    F3 d0[DX];
+    adj_plane_load<DX, Stream>(plane0, off, d0);
+    if constexpr (kAhead == 1) {
+      for (int z = b.z0; z < b.ze; ++z) consume(d0, z);
+    } else {
+      F3 d1[DX];
+      if (b.z0 + 1 < b.ze) adj_plane_load<DX, Stream>(plane(b.z0 + 1), off, d1);
+      for (int z = b.z0; z < b.ze; z += 2) {
+        consume(d0, z);
+        if (z + 1 >= b.ze) break;
+        consume(d1, z + 1);
+      }
     }
   } else {
     for (int z = b.z0; z < b.ze; ++z) {
@@ -452,8 +486,22 @@ struct AdjSpan {
   int lo, hi;  // brick range
 };
 
-__device__ __forceinline__ AdjSpan adj_span(const AdjAxis& ax, int c, int d, int n) {
-  return AdjSpan{adj_brick_of_voxel(ax, max(0, (c - 3) * d)), adj_brick_of_voxel(ax, min(n, (c + 1) * d) - 1)};
+// First control index of brick b's window (b < nb): its first voxel's tile,
+// b * k when the units are whole tiles.
+__host__ __device__ inline int adj_brick_c0(const AdjAxis& ax, int b, int d) {
+  return ax.u == d ? b * ax.k : (b * ax.w) / d;
+}
+
+__host__ __device__ inline AdjSpan adj_span(const AdjAxis& ax, int c, int d, int n) {
+  return AdjSpan{adj_brick_of_voxel(ax, imax(0, (c - 3) * d)), adj_brick_of_voxel(ax, imin(n, (c + 1) * d) - 1)};
+}
+
+// Workspace offset (floats) of control point (cx, cy, cz) in brick (bx, by, bz)'s partials.
+__host__ __device__ inline size_t adj_part_addr(const AdjGeom& a, int bx, int by, int bz, int cx, int cy, int cz) {
+  const int cxl = cx - adj_brick_c0(a.x, bx, a.g.dx);
+  const int cyl = cy - adj_brick_c0(a.y, by, a.g.dy);
+  const int czl = cz - adj_brick_c0(a.z, bz, a.g.dz);
+  return (size_t)((bz * a.y.nb + by) * a.x.nb + bx) * adj_brick_stride(a) + adj_part_offset(a, czl, cyl, cxl);
 }
 
 __device__ __forceinline__ F3 adj_gather_point(const float* __restrict__ part, const AdjGeom& a, int cx,
@@ -461,14 +509,7 @@ __device__ __forceinline__ F3 adj_gather_point(const float* __restrict__ part, c
   const VolGeom& g = a.g;
   const AdjSpan sx = adj_span(a.x, cx, g.dx, g.nx), sy = adj_span(a.y, cy, g.dy, g.ny),
                 sz = adj_span(a.z, cz, g.dz, g.nz);
-  const size_t bstride = (size_t)a.z.cm * a.y.cm * a.x.cm * 3;
-  auto addr = [&](int bx, int by, int bz) {
-    const int cxl = cx - adj_brick_begin(a.x, g.nx, bx) / g.dx;
-    const int cyl = cy - adj_brick_begin(a.y, g.ny, by) / g.dy;
-    const int czl = cz - adj_brick_begin(a.z, g.nz, bz) / g.dz;
-    return part + (size_t)((bz * a.y.nb + by) * a.x.nb + bx) * bstride +
-           ((size_t)(czl * a.y.cm + cyl) * a.x.cm + cxl) * 3;
-  };
+  auto addr = [&](int bx, int by, int bz) { return part + adj_part_addr(a, bx, by, bz, cx, cy, cz); };
   F3 s{0.f, 0.f, 0.f};
   if (sx.hi - sx.lo <= 1 && sy.hi - sy.lo <= 1 && sz.hi - sz.lo <= 1) {
     F3 v[2][2][2];

@@ -20,6 +20,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <unistd.h>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -206,6 +207,18 @@ int32_t check_device(const bsi_batch* p) {
   return BSI_OK;
 }
 
+// Wait until nothing the plan has enqueued is still running: its graph may be
+// replaying and its kernels read the descriptor tables, on the caller's streams
+// as well as on the plan's own.  A launch on a caller's stream cannot be named
+// from here, so the whole device is synchronised.  Called before the graph is
+// destroyed or the tables are rewritten (bind, tune, capture, destroy).
+int32_t quiesce(bsi_batch* p) {
+  const hipError_t e = hipDeviceSynchronize();
+  return e == hipSuccess ? BSI_OK : hip_fail(e, "synchronising the plan's device");
+}
+
+// Callers quiesce first: an executable graph must not be destroyed while a
+// launch of it may still run.
 void drop_graph(bsi_batch* p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
@@ -367,7 +380,11 @@ void cache_store(const char* path, const std::string& key, int value) {
       found = true;
     }
   if (!found) entries.emplace_back(key, value);
-  const std::string tmp = std::string(path) + ".tmp";
+  // a temporary file of this process and call, renamed over the cache: two
+  // processes tuning at once each replace the file whole (the last one wins)
+  static int serial = 0;
+  const std::string tmp = std::string(path) + ".tmp." + std::to_string((long)getpid()) + "." +
+                          std::to_string(++serial);
   {
     std::ofstream f(tmp);
     f << "{\n";
@@ -376,6 +393,15 @@ void cache_store(const char* path, const std::string& key, int value) {
     f << "}\n";
   }
   std::rename(tmp.c_str(), path);
+}
+
+// A schedule index in [0, kNumSchedules), written as a plain decimal number.
+bool parse_schedule(const char* text, int* out) {
+  char* end = nullptr;
+  const long v = std::strtol(text, &end, 10);
+  if (end == text || *end != '\0' || v < 0 || v >= kNumSchedules) return false;
+  *out = (int)v;
+  return true;
 }
 
 std::string plan_key(const bsi_batch* p) {
@@ -496,8 +522,14 @@ int32_t bsi_batch_create(int32_t count, const int32_t* dims3xN, const int32_t* s
     }
   p->key = plan_key(p);
   if (const char* force = std::getenv("BSI_FORCE_CONFIG")) {
-    const int v = std::atoi(force);
-    if (v >= 0 && v < kNumSchedules) p->schedule = v;
+    int v = -1;
+    if (!parse_schedule(force, &v)) {
+      bsi_batch_destroy(p);
+      set_error(std::string("BSI_FORCE_CONFIG=") + force + " is not a schedule index in [0, " +
+                std::to_string(kNumSchedules) + ")");
+      return BSI_ERR_INVALID_ARG;
+    }
+    p->schedule = v;
   } else if (const char* path = std::getenv("BSI_TUNE_CACHE")) {
     const int v = cache_lookup(path, p->key);
     if (v >= 0 && v < kNumSchedules) p->schedule = v;
@@ -525,6 +557,7 @@ int32_t bsi_batch_bind(bsi_batch* p, const float* const* grids, float* const* fi
   }
   int32_t rc = check_device(p);
   if (rc) return rc;
+  if ((rc = quiesce(p))) return rc;
   for (int i = 0; i < p->count; ++i) {
     VolDesc& d = p->host[i];
     d.grid = grids ? grids[i] : nullptr;
@@ -599,13 +632,17 @@ int32_t bsi_batch_tune(bsi_batch* p, hipStream_t stream) {
   }
   int32_t rc = check_device(p);
   if (rc) return rc;
+  if ((rc = quiesce(p))) return rc;
   if (const char* force = std::getenv("BSI_FORCE_CONFIG")) {
-    const int v = std::atoi(force);
-    if (v >= 0 && v < kNumSchedules) {
-      p->schedule = v;
-      drop_graph(p);
-      return BSI_OK;
+    int v = -1;
+    if (!parse_schedule(force, &v)) {
+      set_error(std::string("BSI_FORCE_CONFIG=") + force + " is not a schedule index in [0, " +
+                std::to_string(kNumSchedules) + ")");
+      return BSI_ERR_INVALID_ARG;
     }
+    p->schedule = v;
+    drop_graph(p);
+    return BSI_OK;
   }
   hipEvent_t t0, t1;
   hipError_t e;
@@ -662,6 +699,7 @@ int32_t bsi_batch_capture(bsi_batch* p, hipStream_t stream) {
   }
   int32_t rc = check_device(p);
   if (rc) return rc;
+  if ((rc = quiesce(p))) return rc;
   return build_graph(p, stream);
 }
 

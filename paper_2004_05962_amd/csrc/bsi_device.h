@@ -31,11 +31,14 @@ struct VolGeom {
 
 // Brick decomposition of the adjoint along one axis: the axis is cut into U
 // units of u voxels (a tile, or a single voxel when a tile is taller than a
-// brick may be), and brick b of nb holds units [b*U/nb, (b+1)*U/nb) (integer
-// division: sizes differ by at most one unit).  cm bounds the number of control
-// points whose support meets one brick (the partial-window stride).
+// brick may be), and brick b of nb holds the k units [b*k, (b+1)*k), the last
+// brick the rest.  A brick is w = k*u voxels wide, so brick boundaries sit at
+// multiples of w: with k = 16 x-tiles of d voxels a brick row is 192 d bytes,
+// a multiple of 64, and rows that start on a 64-byte boundary are cut only at
+// 64-byte boundaries.  cm bounds the number of control points whose support
+// meets one brick (the partial-window stride).
 struct AdjAxis {
-  int32_t u, U, nb, cm;
+  int32_t u, U, k, nb, w, cm;
 };
 
 // The adjoint's bricks (see adjoint_device.h).  A pure function of the
@@ -45,14 +48,19 @@ struct AdjGeom {
   AdjAxis x, y, z;
 };
 
+// First voxel of brick b (b <= nb; brick nb begins at the axis end n).  For
+// b < nb this is b * w < n, since b * k < U.  Axes hold at most 2^20 voxels,
+// so b * w fits 32 bits.
 __host__ __device__ __forceinline__ int adj_brick_begin(const AdjAxis& a, int n, int b) {
-  const int v = (int)(((int64_t)b * a.U / a.nb) * a.u);
+  const int v = b * a.w;
   return v < n ? v : n;
 }
-__host__ __device__ __forceinline__ int adj_brick_of_voxel(const AdjAxis& a, int v) {
-  const int t = v / a.u;
-  return (int)(((int64_t)(t + 1) * a.nb - 1) / a.U);
-}
+__host__ __device__ __forceinline__ int adj_brick_of_voxel(const AdjAxis& a, int v) { return v / a.w; }
+
+// Integer min / max callable from host code too (the host index checker runs
+// the kernels' address arithmetic on the CPU).
+__host__ __device__ constexpr int imin(int a, int b) { return a < b ? a : b; }
+__host__ __device__ constexpr int imax(int a, int b) { return a > b ? a : b; }
 
 __device__ __forceinline__ const float* lut_row(const float* lut, int d, int o) {
   return lut + 4 * ((d * (d - 1)) / 2 + o);
@@ -133,6 +141,21 @@ struct FwdSmem {
   float ring[2][fwd_loads<C, T>() * T::threads];
 };
 
+// Control points a forward workgroup of `width` voxels x `rows` rows at
+// (x0, y0) reads from each plane: columns cx0 .. cx0 + ncx - 1, rows
+// cy0 .. cy0 + ncy - 1 (the tiles of its voxels plus 3).
+struct FwdWindow {
+  int cx0, ncx, cy0, ncy;
+};
+__host__ __device__ inline FwdWindow fwd_window(const VolGeom& g, int x0, int y0, int width, int rows) {
+  FwdWindow w;
+  w.cx0 = x0 / g.dx;
+  w.ncx = (imin(x0 + width, g.nx) - 1) / g.dx - w.cx0 + 4;
+  w.cy0 = y0 / g.dy;
+  w.ncy = (imin(y0 + rows, g.ny) - 1) / g.dy - w.cy0 + 4;
+  return w;
+}
+
 // Staging map: thread tid moves floats e = tid + k * threads of the window,
 // e = row * pitch + col; goff[k] is its grid offset within a plane, or -1 when
 // e lies outside this workgroup's window.
@@ -142,7 +165,7 @@ struct FwdStage {
 };
 
 template <int C, class T = FwdTileDefault>
-__device__ __forceinline__ FwdStage<C, T> fwd_stage_map(const VolGeom& g, int cx0, int ncx, int cy0, int ncy,
+__host__ __device__ inline FwdStage<C, T> fwd_stage_map(const VolGeom& g, int cx0, int ncx, int cy0, int ncy,
                                                         int tid) {
   FwdStage<C, T> m;
 #pragma unroll
@@ -305,11 +328,9 @@ __device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float*
   static_assert(!Edge || V == 1, "edge stores assume one voxel per lane");
   const int lane = tid & (kWave - 1);
   const int wave = uniform(tid / kWave);
-  const int cx0 = x0 / g.dx;
-  const int ncx = (min(x0 + T::width, g.nx) - 1) / g.dx - cx0 + 4;
-  const int cy0 = y0 / g.dy;
-  const int ncy = (min(y0 + T::rows, g.ny) - 1) / g.dy - cy0 + 4;
-  const FwdStage<C, T> map = fwd_stage_map<C, T>(g, cx0, ncx, cy0, ncy, tid);
+  const FwdWindow win = fwd_window(g, x0, y0, T::width, T::rows);
+  const int cx0 = win.cx0, cy0 = win.cy0;
+  const FwdStage<C, T> map = fwd_stage_map<C, T>(g, cx0, win.ncx, cy0, win.ncy, tid);
 
   const int xl = x0 + (wave % T::strips) * kWave * V + V * lane;  // the lane's first voxel
   const int y = y0 + wave / T::strips;
@@ -426,6 +447,103 @@ __device__ __forceinline__ void fwd_block(const float* __restrict__ grid, float*
       q0[k] = q1[k];
       q1[k] = q2[k];
       q2[k] = q3[k];
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// Forward BSI, one span per workgroup: rows [y0, y1) of voxel plane z, i.e.
+// (y1 - y0) * nx consecutive voxels, a contiguous range of the field.  The
+// workgroup writes its span and exits; consecutive workgroups take consecutive
+// spans, so the writes in flight at any moment cover one compact range of
+// addresses, as in a plain fill.
+//
+// Sum factorisation of Eq. 1 in the order z, y, x, through LDS:
+//   P[r][c]  = sum_n Bz_n(w) * phi[tz+n][ty0+r][c]          (control rows r < nry)
+//   Q[ry][c] = sum_m By_m(v(y0+ry)) * P[ty(y0+ry)-ty0+m][c] (span rows ry)
+//   T        = sum_l Bx_l(u(x)) * Q[ry][tx+l]               (per voxel)
+// (c runs over the gx * C floats of a control row).  The four control planes
+// of the span stay in L2 for the neighbouring spans of the same planes.
+// Lane = voxel: each of the 256 threads takes voxels x = tid + 256 k of every
+// row, so a wave writes 64 consecutive voxels per store instruction.  Stores
+// are non-temporal, except for voxels in a 64-byte segment the span shares with
+// the neighbouring span (its first and last segment, when the span does not
+// start or end on a 64-byte boundary), which use ordinary stores so that the
+// two halves meet in L2.  LDS: (nry + rows) * gx * C floats (fwd_span_lds).
+// ----------------------------------------------------------------------------
+constexpr int kSpanThreads = 256;
+
+__host__ __device__ constexpr int fwd_span_ctl_rows(int rows, int dy) { return (rows - 1) / dy + 5; }
+__host__ __device__ constexpr size_t fwd_span_lds(int rows, int dy, int gx, int C) {
+  return (size_t)(fwd_span_ctl_rows(rows, dy) + rows) * gx * C * sizeof(float);
+}
+
+// The control window of span (z, rows [y0, y1)): planes tz .. tz+3, control
+// rows ty0 .. ty0 + nry - 1, all gx columns.
+struct FwdSpanWindow {
+  int tz, ty0, nry;
+};
+__host__ __device__ inline FwdSpanWindow fwd_span_window(const VolGeom& g, int z, int y0, int y1) {
+  FwdSpanWindow w;
+  w.tz = z / g.dz;
+  w.ty0 = y0 / g.dy;
+  w.nry = (y1 - 1) / g.dy - w.ty0 + 4;
+  return w;
+}
+
+template <int C>
+__device__ __forceinline__ void fwd_span(const float* __restrict__ grid, float* __restrict__ field, const VolGeom& g,
+                                         const float* __restrict__ lut, int z, int y0, int y1,
+                                         float* __restrict__ smem, int tid) {
+  const int W = g.gx * C;  // floats per control row
+  const FwdSpanWindow win = fwd_span_window(g, z, y0, y1);
+  const int tz = win.tz, ty0 = win.ty0, nry = win.nry;
+  const float* wz = lut_row(lut, g.dz, z - tz * g.dz);
+  const float z0 = wz[0], z1 = wz[1], z2 = wz[2], z3 = wz[3];
+  const int rows = y1 - y0;
+  float* P = smem;             // [nry][W]
+  float* Q = smem + nry * W;   // [rows][W]
+  const size_t pstride = (size_t)g.gy * W;
+  const float* g0 = grid + ((size_t)tz * g.gy + ty0) * W;
+  for (int e = tid; e < nry * W; e += kSpanThreads) {
+    const float* q = g0 + e;  // control row ty0 + e / W, float e % W of plane tz
+    P[e] = fmaf(z3, q[3 * pstride], fmaf(z2, q[2 * pstride], fmaf(z1, q[pstride], z0 * q[0])));
+  }
+  __syncthreads();
+  for (int e = tid; e < rows * W; e += kSpanThreads) {
+    const int ry = e / W;
+    const int i = e - ry * W;
+    const int y = y0 + ry;
+    const int ty = y / g.dy;
+    const float* wy = lut_row(lut, g.dy, y - ty * g.dy);
+    const float* p = P + (ty - ty0) * W + i;
+    Q[e] = fmaf(wy[3], p[3 * W], fmaf(wy[2], p[2 * W], fmaf(wy[1], p[W], wy[0] * p[0])));
+  }
+  __syncthreads();
+  // the span's bytes [sb, se) relative to a 64-byte boundary below them
+  const uintptr_t sb = reinterpret_cast<uintptr_t>(field + ((size_t)z * g.ny + y0) * g.nx * C);
+  const int m = (int)(sb & 63);
+  const long nvox = (long)rows * g.nx;
+  const long head = m ? (64 - m + 4 * C - 1) / (4 * C) : 0;         // voxels in the shared first segment
+  const long end = m + nvox * 4 * C;
+  const long tail = (end & 63) ? ((end & ~63L) - m) / (4 * C) : nvox;  // first voxel in the shared last segment
+  // both kinds of store are buffer stores over the span (a span holds fewer
+  // than 2^32 bytes: rows * nx * C * 4 with rows * nx below 2^28)
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      field + ((size_t)z * g.ny + y0) * g.nx * C, 0, (int)(nvox * 4 * C), kBufferFlags);
+  for (int ry = 0; ry < rows; ++ry) {
+    const float* q = Q + ry * W;
+    for (int x = tid; x < g.nx; x += kSpanThreads) {
+      const int tx = x / g.dx;
+      const float* wx = lut_row(lut, g.dx, x - tx * g.dx);
+      const float* p = q + tx * C;
+      float t[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+        t[c] = fmaf(wx[3], p[3 * C + c], fmaf(wx[2], p[2 * C + c], fmaf(wx[1], p[C + c], wx[0] * p[c])));
+      const long v = (long)ry * g.nx + x;
+      if (v >= head && v < tail) fwd_buffer_store<C>(rs, (int)(v * 4 * C), t, kCpolNT);
+      else fwd_buffer_store<C>(rs, (int)(v * 4 * C), t, 0);
     }
   }
 }

@@ -26,6 +26,7 @@ int32_t lerp_lut_device_ptr(int dev, const float** out);
 
 // Host-side geometry helpers.
 int32_t make_geom(const int32_t dims[3], const int32_t spacing[3], VolGeom* g);
+int32_t check_control_plane(int32_t gx, int32_t gy);  // UNSUPPORTED at 2^31 floats or more
 AdjGeom make_adj_geom(const VolGeom& g);
 size_t adj_workspace_bytes(const AdjGeom& a);
 
@@ -39,6 +40,8 @@ struct FwdLaunch {
 constexpr int kFwdTargetBlocks = BSI_FWD_BLOCKS; // z is split until this many workgroups
 // width x rows: the voxels and rows one workgroup covers in x and y.
 FwdLaunch make_fwd_launch(const VolGeom& g, long target = kFwdTargetBlocks, int width = kWave, int rows = kFwdRows);
+// Rows per span of the span forward (fwd_span), 0 when a span of one row does not fit.
+int span_rows(const VolGeom& g, int C);
 
 hipError_t launch_forward(const float* grid, float* field, const VolGeom& g, const float* lut,
                           hipStream_t s);
@@ -66,7 +69,7 @@ hipError_t launch_ssd_fused(const float* grid, const float* moving, const float*
 // Real spacing s and origin o per axis (general.hip): control point a at voxel
 // o + (a - 1) s, n voxels, g control points.
 struct GenAxis {
-  double s, o;
+  float s, o;  // the caller's FP32 spacing and origin
   int n, g;
 };
 struct GenGeom {

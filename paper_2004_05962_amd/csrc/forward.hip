@@ -33,6 +33,46 @@ hipError_t launch_fwd(const float* grid, float* field, const VolGeom& g, const f
   return hipGetLastError();
 }
 
+// One span (rows [yb * R, yb * R + R) of plane z) per workgroup, workgroup id =
+// z * nyb + yb: ids follow the field's addresses.
+template <int C>
+__global__ __launch_bounds__(kSpanThreads) void fwd_span_kernel(const float* __restrict__ grid,
+                                                                 float* __restrict__ field, VolGeom g,
+                                                                 const float* __restrict__ lut, int R, int nyb) {
+  extern __shared__ float span_smem[];
+  const int z = blockIdx.x / nyb;
+  const int yb = blockIdx.x - z * nyb;
+  const int y0 = yb * R;
+  fwd_span<C>(grid, field, g, lut, z, y0, min(g.ny, y0 + R), span_smem, threadIdx.x);
+}
+
+#ifndef BSI_FWD_SPAN_VOXELS
+#define BSI_FWD_SPAN_VOXELS 2048
+#endif
+#ifndef BSI_FWD_SPAN_LDS
+#define BSI_FWD_SPAN_LDS 32768
+#endif
+
+// Rows per span: the most (up to about BSI_FWD_SPAN_VOXELS voxels) whose LDS
+// fits BSI_FWD_SPAN_LDS bytes; 0 when not even one row fits (very wide rows).
+int span_rows(const VolGeom& g, int C) {
+  int R = BSI_FWD_SPAN_VOXELS / g.nx;
+  if (R < 1) R = 1;
+  if (R > g.ny) R = g.ny;
+  while (R >= 1 && fwd_span_lds(R, g.dy, g.gx, C) > BSI_FWD_SPAN_LDS) --R;
+  if (R >= 1 && (double)R * g.nx * C * 4 >= 2147483648.0) return 0;
+  return R;
+}
+
+template <int C>
+hipError_t launch_span(const float* grid, float* field, const VolGeom& g, const float* lut, int R, hipStream_t s) {
+  const int nyb = (g.ny + R - 1) / R;
+  const long blocks = (long)nyb * g.nz;
+  hipLaunchKernelGGL(fwd_span_kernel<C>, dim3((unsigned)blocks), dim3(kSpanThreads),
+                     fwd_span_lds(R, g.dy, g.gx, C), s, grid, field, g, lut, R, nyb);
+  return hipGetLastError();
+}
+
 FwdLaunch make_fwd_launch(const VolGeom& g, long target, int width, int rows) {
   FwdLaunch L;
   L.nbx = (g.nx + width - 1) / width;
@@ -61,6 +101,12 @@ FwdLaunch make_fwd_launch(const VolGeom& g, long target, int width, int rows) {
 // spacing 3 (0.224 against 0.189 ms).  Other rows take edge stores (fwd_block).
 hipError_t launch_forward(const float* grid, float* field, const VolGeom& g, const float* lut,
                           hipStream_t s) {
+#if BSI_FWD_SPAN
+  {
+    const int R = span_rows(g, 3);
+    if (R > 0 && (long)((g.ny + R - 1) / R) * g.nz < 0x7fffffffL) return launch_span<3>(grid, field, g, lut, R, s);
+  }
+#endif
   const bool aligned = (g.nx * 12) % 64 == 0 && reinterpret_cast<uintptr_t>(field) % 64 == 0;
   if (aligned && g.nx > 256 && g.dz >= 5)
     return launch_fwd<3, FwdTile<2, 8, 1>, false>(grid, field, g, lut, s);

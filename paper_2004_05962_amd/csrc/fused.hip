@@ -156,7 +156,11 @@ __device__ __forceinline__ void fused_brick(const float* __restrict__ grid, cons
         if (txl < 3) stf3(pl + (r * kFusedCols + kAdjTilesX + txl) * 3, pw);
       }
       wave_lds_sync();
+#if BSI_FUSED_FULL_UNROLL
+#pragma unroll
+#else
 #pragma unroll 2
+#endif
       for (int k = 0; k < DX; ++k) {
         const int v = k * kWave + lane;
         const int r = v / (kAdjTilesX * DX);

@@ -4,9 +4,11 @@
 //   control point a sits at voxel o + (a - 1) s      (s >= 1, -s < o <= 0),
 //   voxel x: t = (x - o) / s, window i = floor(t) .. i + 3, weights B(t - i),
 //   g = floor((n - 1 - o) / s) + 4 points.
-// t is formed in FP64 from the FP32 values of s and o, the same two IEEE
-// operations on the host and the device, so every window decision agrees; the
-// weights are evaluated in FP64 and rounded to FP32.
+// The window start i = floor((x - o)/s) is decided exactly, from the FP32
+// values of s and o, with FP32 error-free transformations (gen_locate); the
+// same code runs on the host (grid size) and the device, so every decision
+// agrees.  The offset u = t - i and the weights are FP32.  Nothing on the
+// device is FP64.
 //
 // Forward: the aligned kernel's pipeline (forward.hip) with weights computed
 // per coordinate instead of looked up per offset: x weights once per lane, y
@@ -28,20 +30,76 @@
 
 namespace bsi {
 
-__host__ __device__ inline double gen_t(const GenAxis& a, int v) { return ((double)v - a.o) / a.s; }
-__host__ __device__ inline int gen_tile(const GenAxis& a, int v) { return (int)floor(gen_t(a, v)); }
+// a + b = s + e exactly (Knuth's two-sum; round to nearest, no overflow).
+__host__ __device__ inline void two_sum(float a, float b, float& s, float& e) {
+  s = a + b;
+  const float bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// Exact sign of D(i) = (x - o) - i s for integers 0 <= x, |i| < 2^24, and the
+// FP32 value of D rounded from its exact expansion.  x - o = A + a and i s =
+// P + p are error-free; growing the nonoverlapping expansion (a, A) by -p and
+// then by -P (Shewchuk's grow-expansion) gives four nonoverlapping components
+// whose largest nonzero one carries the sign of the exact sum.
+__host__ __device__ inline int gen_residual(float X, float o, float s, int i, float& D) {
+  float A, a;
+  two_sum(X, -o, A, a);
+  const float I = (float)i;
+  const float P = I * s;
+  const float p = fmaf(I, s, -P);
+  float Q, h0, h1, k0, k1, k2;
+  two_sum(-p, a, Q, h0);
+  two_sum(Q, A, Q, h1);
+  const float h2 = Q;
+  two_sum(-P, h0, Q, k0);
+  two_sum(Q, h1, Q, k1);
+  two_sum(Q, h2, Q, k2);
+  const float k3 = Q;
+  D = k3 + k2;
+  const float top = k3 != 0.f ? k3 : k2 != 0.f ? k2 : k1 != 0.f ? k1 : k0;
+  return top > 0.f ? 1 : top < 0.f ? -1 : 0;
+}
+
+// Window start i = floor((v - o)/s) of voxel v (exact) and u = (v - o)/s - i
+// in FP32.  The FP32 quotient is within 1/8 of the exact one for v < 2^21, so
+// the floor is its floor, one below or one above; the exact residual decides.
+__host__ __device__ inline int gen_locate(const GenAxis& a, int v, float& u) {
+  const float X = (float)v;
+  int i = (int)floorf((X - a.o) / a.s);
+  float D;
+  if (gen_residual(X, a.o, a.s, i, D) < 0) {
+    --i;
+    (void)gen_residual(X, a.o, a.s, i, D);
+  } else {
+    float D1;
+    if (gen_residual(X, a.o, a.s, i + 1, D1) >= 0) {
+      ++i;
+      D = D1;
+    }
+  }
+  u = D / a.s;
+  return i;
+}
+
+__host__ __device__ inline int gen_tile(const GenAxis& a, int v) {
+  float u;
+  return gen_locate(a, v, u);
+}
 
 namespace {
 
+// Window start and the four FP32 basis weights at u (B0..B3 of Eq. 1).
 __device__ __forceinline__ int gen_weights(const GenAxis& a, int v, float (&w)[4]) {
-  const double t = gen_t(a, v);
-  const double fi = floor(t);
-  const double u = t - fi, r = 1.0 - u, u2 = u * u, u3 = u2 * u;
-  w[0] = (float)(r * r * r / 6.0);
-  w[1] = (float)((3.0 * u3 - 6.0 * u2 + 4.0) / 6.0);
-  w[2] = (float)((-3.0 * u3 + 3.0 * u2 + 3.0 * u + 1.0) / 6.0);
-  w[3] = (float)(u3 / 6.0);
-  return (int)fi;
+  float u;
+  const int i = gen_locate(a, v, u);
+  const float r = 1.f - u, u2 = u * u;
+  const float sixth = 1.f / 6.f;
+  w[0] = r * r * r * sixth;
+  w[1] = fmaf(3.f * u2, u - 2.f, 4.f) * sixth;
+  w[2] = fmaf(3.f * u, fmaf(-u, u, u) + 1.f, 1.f) * sixth;
+  w[3] = u2 * u * sixth;
+  return i;
 }
 
 constexpr int kGenMaxZ = 256;  // voxel planes per workgroup (z table in LDS)
@@ -366,7 +424,12 @@ int32_t make_gen_geom(const int32_t dims[3], const float spacing[3], const float
   g->gx = q->x.g;
   g->gy = q->y.g;
   g->gz = q->z.g;
-  return BSI_OK;
+  // the forward's staging map is the aligned forward's (signed 32-bit offsets)
+  if ((double)g->nx * g->ny * 3 >= 4294967296.0) {
+    set_error("a voxel plane (nx * ny) above 1.43e9 voxels");
+    return BSI_ERR_UNSUPPORTED;
+  }
+  return check_control_plane(g->gx, g->gy);
 }
 
 hipError_t launch_forward_general(const float* grid, float* field, const VolGeom& g, const GenGeom& q,

@@ -1,0 +1,224 @@
+// Host-side check of the kernels' index arithmetic (test infrastructure).
+//
+// Runs, on the CPU, the same geometry functions and __host__ __device__
+// address helpers the kernels use, for every workgroup / lane / control point
+// of a launch, and checks that every global load and store lies inside its
+// buffer (dfield, field, grid, workspace), that every LDS index lies inside
+// its array, and that pass 2 reads only partials pass 1 wrote.  Nothing here
+// touches a device.  Built next to libbsi.so and called by the CPU tests.
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "adjoint_device.h"
+#include "bsi_internal.h"
+
+namespace bsi {
+namespace {
+
+struct Check {
+  std::string msg;
+  bool ok = true;
+  bool fail(const std::string& m) {
+    if (ok) msg = m;
+    ok = false;
+    return false;
+  }
+};
+
+#define REQUIRE(c, what)                                                         \
+  do {                                                                           \
+    if (!(c)) return ck.fail(std::string(what) + " [" #c "]");                   \
+  } while (0)
+
+template <int DX>
+bool check_plane_offsets(const AdjGeom& a, const AdjBrick& b, Check& ck) {
+  const size_t plane = (size_t)a.g.nx * a.g.ny * 3;
+  for (int w = 0; w < kAdjWaves; ++w)
+    for (int lane = 0; lane < kWave; ++lane) {
+      uint32_t off[DX];
+      adj_plane_offsets<DX>(b, a.g.nx, b.y0 + w * kAdjRowsPerWave, lane, off);
+      for (int k = 0; k < DX; ++k) {
+        REQUIRE((size_t)off[k] + 3 <= plane, "pass-1 load outside its voxel plane");
+        const int x = (int)(off[k] / 3 % a.g.nx), y = (int)(off[k] / 3 / a.g.nx);
+        REQUIRE(x >= b.x0 && x < b.xe && y >= b.y0 && y < b.ye, "pass-1 load outside its brick");
+      }
+    }
+  return true;
+}
+
+bool check_loads(const AdjGeom& a, const AdjBrick& b, Check& ck) {
+  switch (a.g.dx) {
+    case 1: return check_plane_offsets<1>(a, b, ck);
+    case 2: return check_plane_offsets<2>(a, b, ck);
+    case 3: return check_plane_offsets<3>(a, b, ck);
+    case 4: return check_plane_offsets<4>(a, b, ck);
+    case 5: return check_plane_offsets<5>(a, b, ck);
+    case 6: return check_plane_offsets<6>(a, b, ck);
+    case 7: return check_plane_offsets<7>(a, b, ck);
+    case 8: return check_plane_offsets<8>(a, b, ck);
+    case 9: return check_plane_offsets<9>(a, b, ck);
+    case 10: return check_plane_offsets<10>(a, b, ck);
+    case 11: return check_plane_offsets<11>(a, b, ck);
+    case 12: return check_plane_offsets<12>(a, b, ck);
+    default: {
+      // generic path: each active lane reads its tile row's nval voxels directly
+      for (int tid = 0; tid < kAdjThreads; ++tid) {
+        const int txl = tid % kAdjTilesX, y = b.y0 + tid / kAdjTilesX, x = (b.cx0 + txl) * a.g.dx;
+        if (txl < b.ntx && y < b.ye) REQUIRE(x >= b.x0 && imin(a.g.dx, a.g.nx - x) + x <= b.xe, "generic load");
+      }
+      return true;
+    }
+  }
+}
+
+// Pass 1 and pass 2 of the adjoint for one geometry.
+bool check_adjoint(const VolGeom& g, Check& ck) {
+  static_assert(kAdjMaxDX == 12, "one case per specialised spacing");
+  const AdjGeom a = make_adj_geom(g);
+  const size_t ws = adj_workspace_bytes(a) / sizeof(float);
+  const int nb = a.x.nb * a.y.nb * a.z.nb;
+  REQUIRE(a.x.nb >= 1 && a.y.nb >= 1 && a.z.nb >= 1, "brick counts");
+  REQUIRE((size_t)nb * adj_brick_stride(a) == ws, "workspace holds the bricks");
+  // the window of every brick, as pass 1 writes it
+  std::vector<int> Cx(nb), Cy(nb), Cz(nb);
+  long voxels = 0;
+  for (int id = 0; id < nb; ++id) {
+    const AdjBrick b = adj_brick_geom(a, id);
+    REQUIRE(0 <= b.x0 && b.x0 < b.xe && b.xe <= g.nx, "brick x range");
+    REQUIRE(0 <= b.y0 && b.y0 < b.ye && b.ye <= g.ny, "brick y range");
+    REQUIRE(0 <= b.z0 && b.z0 < b.ze && b.ze <= g.nz, "brick z range");
+    REQUIRE(b.ntx >= 1 && b.ntx <= kAdjTilesX, "x-tiles per brick (one lane each)");
+    REQUIRE(b.ye - b.y0 <= kAdjMaxY, "rows per brick (one lane row each)");
+    REQUIRE(b.x0 == b.cx0 * g.dx, "x-bricks start on tile boundaries");
+    REQUIRE(b.Cx <= a.x.cm && b.Cx <= kAdjMaxCx, "x window (partials stride, LDS slot)");
+    REQUIRE(b.Cy <= a.y.cm && b.Cy <= kAdjMaxCy, "y window (partials stride, LDS tables)");
+    const int cz = adj_brick_cz(a, b);
+    REQUIRE(cz <= a.z.cm, "z window (partials stride)");
+    REQUIRE(b.cx0 + b.Cx <= g.gx && b.cy0 + b.Cy <= g.gy && b.cz0 + cz <= g.gz, "window inside the grid");
+    REQUIRE(b.cx0 == adj_brick_c0(a.x, id % a.x.nb, g.dx), "x window start");
+    REQUIRE(b.cy0 == adj_brick_c0(a.y, id / a.x.nb % a.y.nb, g.dy), "y window start");
+    REQUIRE(b.cz0 == adj_brick_c0(a.z, id / (a.x.nb * a.y.nb), g.dz), "z window start");
+    const size_t last = (size_t)id * adj_brick_stride(a) + adj_part_offset(a, cz - 1, b.Cy - 1, b.Cx - 1);
+    REQUIRE(last + 3 <= ws, "partial store outside the workspace");
+    if (!check_loads(a, b, ck)) return false;
+    Cx[id] = b.Cx;
+    Cy[id] = b.Cy;
+    Cz[id] = cz;
+    voxels += (long)(b.xe - b.x0) * (b.ye - b.y0) * (b.ze - b.z0);
+  }
+  REQUIRE(voxels == (long)g.nx * g.ny * g.nz, "bricks tile the volume");
+  // per axis: brick b meets the support [(c-3)d, (c+1)d) of control index c
+  // exactly when b lies in c's span (pass 2 misses no brick and adds no other)
+  const AdjAxis* axes[3] = {&a.x, &a.y, &a.z};
+  const int nn[3] = {g.nx, g.ny, g.nz}, dd[3] = {g.dx, g.dy, g.dz}, gg[3] = {g.gx, g.gy, g.gz};
+  for (int ax = 0; ax < 3; ++ax)
+    for (int c = 0; c < gg[ax]; ++c) {
+      const AdjSpan sp = adj_span(*axes[ax], c, dd[ax], nn[ax]);
+      const int lo = imax(0, (c - 3) * dd[ax]), hi = imin(nn[ax], (c + 1) * dd[ax]);
+      for (int b = 0; b < axes[ax]->nb; ++b) {
+        const int b0 = adj_brick_begin(*axes[ax], nn[ax], b), b1 = adj_brick_begin(*axes[ax], nn[ax], b + 1);
+        const bool meets = b0 < hi && lo < b1;
+        REQUIRE(meets == (b >= sp.lo && b <= sp.hi), "pass-2 span differs from the bricks meeting the support");
+      }
+    }
+  // pass 2: every brick a control point reads holds that point in its window
+  for (int cz = 0; cz < g.gz; ++cz)
+    for (int cy = 0; cy < g.gy; ++cy)
+      for (int cx = 0; cx < g.gx; ++cx) {
+        const AdjSpan sx = adj_span(a.x, cx, g.dx, g.nx), sy = adj_span(a.y, cy, g.dy, g.ny),
+                      sz = adj_span(a.z, cz, g.dz, g.nz);
+        REQUIRE(0 <= sx.lo && sx.lo <= sx.hi && sx.hi < a.x.nb, "x span");
+        REQUIRE(0 <= sy.lo && sy.lo <= sy.hi && sy.hi < a.y.nb, "y span");
+        REQUIRE(0 <= sz.lo && sz.lo <= sz.hi && sz.hi < a.z.nb, "z span");
+        for (int bz = sz.lo; bz <= sz.hi; ++bz)
+          for (int by = sy.lo; by <= sy.hi; ++by)
+            for (int bx = sx.lo; bx <= sx.hi; ++bx) {
+              const int id = (bz * a.y.nb + by) * a.x.nb + bx;
+              const int cxl = cx - adj_brick_c0(a.x, bx, g.dx), cyl = cy - adj_brick_c0(a.y, by, g.dy),
+                        czl = cz - adj_brick_c0(a.z, bz, g.dz);
+              REQUIRE(0 <= cxl && cxl < Cx[id] && 0 <= cyl && cyl < Cy[id] && 0 <= czl && czl < Cz[id],
+                      "pass 2 reads a partial pass 1 did not write");
+              REQUIRE(adj_part_addr(a, bx, by, bz, cx, cy, cz) + 3 <= ws, "pass-2 load outside the workspace");
+            }
+      }
+  return true;
+}
+
+// The marching forward (fwd_block) with workgroup shape T and C components.
+template <int C, class T>
+bool check_forward_march(const VolGeom& g, Check& ck) {
+  const FwdLaunch L = make_fwd_launch(g, kFwdTargetBlocks, T::width, T::rows);
+  REQUIRE(L.zchunk % g.dz == 0 && L.zchunk > 0, "z chunks of whole tiles");
+  REQUIRE((long)L.nbz * L.zchunk >= g.nz && (long)(L.nbz - 1) * L.zchunk < g.nz, "z chunks cover the volume");
+  const size_t cplane = (size_t)g.gx * g.gy * C;
+  for (int bz = 0; bz < L.nbz; ++bz)
+    for (int by = 0; by < L.nby; ++by)
+      for (int bx = 0; bx < L.nbx; ++bx) {
+        const int x0 = bx * T::width, y0 = by * T::rows, z0 = bz * L.zchunk, z1 = imin(g.nz, z0 + L.zchunk);
+        REQUIRE(x0 < g.nx && y0 < g.ny && z0 < z1, "forward workgroup inside the volume");
+        const FwdWindow w = fwd_window(g, x0, y0, T::width, T::rows);
+        REQUIRE(w.ncx <= T::max_cx && w.ncy <= T::max_cy, "forward window within the staging capacity");
+        REQUIRE(w.cx0 + w.ncx <= g.gx && w.cy0 + w.ncy <= g.gy, "forward window inside the grid");
+        // planes read: tiles z0/dz .. (z1-1)/dz, each with its 3 successors
+        REQUIRE((z1 - 1) / g.dz + 3 < g.gz, "forward planes inside the grid");
+        if (bz == 0 && by == 0)  // the staging map depends on the column window only through cx0, ncx
+          for (int tid = 0; tid < T::threads; ++tid) {
+            const FwdStage<C, T> m = fwd_stage_map<C, T>(g, w.cx0, w.ncx, w.cy0, w.ncy, tid);
+            for (int k = 0; k < fwd_loads<C, T>(); ++k)
+              REQUIRE(m.goff[k] < 0 || (size_t)m.goff[k] < cplane, "staged load outside its control plane");
+          }
+      }
+  return true;
+}
+
+// The span forward: every span's control window and LDS request.
+template <int C>
+bool check_forward_span(const VolGeom& g, Check& ck) {
+  const int R = span_rows(g, C);
+  if (R == 0) return true;  // the span kernel is not used for this geometry
+  REQUIRE((double)R * g.nx * C * 4 < 2147483648.0, "span bytes fit the buffer record");
+  REQUIRE((g.nx - 1) / g.dx + 3 < g.gx, "span columns inside the grid");
+  const int nyb = (g.ny + R - 1) / R;
+  for (int yb = 0; yb < nyb; ++yb) {
+    const int y0 = yb * R, y1 = imin(g.ny, y0 + R);
+    REQUIRE(y0 < y1, "span rows inside the volume");
+    for (int z = 0; z < g.nz; ++z) {
+      const FwdSpanWindow w = fwd_span_window(g, z, y0, y1);
+      REQUIRE(w.tz + 3 < g.gz, "span planes inside the grid");
+      REQUIRE(w.ty0 + w.nry <= g.gy, "span control rows inside the grid");
+      REQUIRE(w.nry <= fwd_span_ctl_rows(R, g.dy), "span window within its LDS request");
+      REQUIRE((size_t)(w.nry + (y1 - y0)) * g.gx * C * sizeof(float) <= fwd_span_lds(R, g.dy, g.gx, C),
+              "span LDS use within the request");
+    }
+  }
+  return true;
+}
+
+bool check_forward(const VolGeom& g, Check& ck) {
+  return check_forward_march<3, FwdTileDefault>(g, ck) && check_forward_march<3, FwdTile<2, 8, 1>>(g, ck) &&
+         check_forward_march<1, FwdTile<kFwdRows, 1, 4>>(g, ck) && check_forward_march<1, FwdTileDefault>(g, ck) &&
+         check_forward_span<3>(g, ck) && check_forward_span<1>(g, ck);
+}
+
+}  // namespace
+}  // namespace bsi
+
+using namespace bsi;
+
+extern "C" {
+
+// 0: every check passed; 1: a check failed (message in msg); -1: invalid geometry.
+int bsi_check_indices(const int32_t dims[3], const int32_t spacing[3], char* msg, int msglen) {
+  VolGeom g;
+  if (make_geom(dims, spacing, &g)) {
+    std::snprintf(msg, msglen, "invalid geometry");
+    return -1;
+  }
+  Check ck;
+  check_adjoint(g, ck) && check_forward(g, ck);
+  std::snprintf(msg, msglen, "%s", ck.msg.c_str());
+  return ck.ok ? 0 : 1;
+}
+
+}  // extern "C"

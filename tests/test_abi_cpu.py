@@ -6,6 +6,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from conftest import ROOT, has_gpu
@@ -145,3 +146,50 @@ def test_every_export_has_a_package_binding():
     """Each C entry point is callable from the package under the same name."""
     missing = [n for n in _lib.EXPORTS if not callable(getattr(bsi, n, None))]
     assert not missing, missing
+
+
+@pytest.mark.parametrize("dims,spacing", [((40000, 20000, 1), (1, 1, 1)), ((30000, 30000, 2), (1, 1, 1))])
+def test_oversized_control_plane_rejected(dims, spacing):
+    # a voxel plane under 2^32 floats whose control plane (gx * gy * 3 floats)
+    # reaches 2^31: the kernels' signed 32-bit staging offsets would wrap
+    with pytest.raises(bsi.BSIError) as e:
+        bsi.bsi_grid_dims(dims, spacing)
+    assert e.value.code == _lib.BSI_ERR_UNSUPPORTED
+    with pytest.raises(bsi.BSIError) as e:
+        bsi.bsi_general_grid_dims(dims, (1.0, 1.0, 1.0), (0.0, 0.0, 0.0))
+    assert e.value.code == _lib.BSI_ERR_UNSUPPORTED
+
+
+def test_batch_bind_checks_list_length_before_the_library():
+    # a plan's geometry is known to the binding; a short list raises before any
+    # pointer reaches the library (no device is needed for this check)
+    fake = ctypes.c_void_p(0x1000)
+    _lib._PLANS[fake.value] = ([(8, 8, 8), (9, 9, 9)], [(2, 2, 2), (3, 3, 3)])
+    try:
+        with pytest.raises(ValueError, match="2 volumes"):
+            _lib.bsi_batch_bind(fake, grids=[None], fields=[None])
+    finally:
+        _lib._PLANS.pop(fake.value)
+    with pytest.raises(ValueError, match="live batched plan"):
+        _lib.bsi_batch_bind(ctypes.c_void_p(0x2000), grids=[], fields=[])
+
+
+def test_general_window_start_is_the_exact_floor():
+    # The library decides floor((x - o)/s) with FP32 error-free arithmetic (the
+    # same routine on host and device); g = floor((n - 1 - o)/s) + 4 exercises it
+    # on the host.  Checked against exact rationals: random geometries, quotients
+    # that are exact integers, and origins far below one ulp of x.
+    from oracle import general
+    rng = np.random.default_rng(17)
+    cases = []
+    for _ in range(400):
+        s = float(np.float32(rng.uniform(1.0, 64.0)))
+        o = float(np.float32(-rng.uniform(0.0, 1.0) * s * 0.999999))
+        n = int(rng.integers(1, 1 << 20))
+        cases.append((n, s, o))
+    for k in range(1, 40):
+        cases += [(int(1.5 * (2 * k - 1) + 1.5), 1.5, -0.5), (2 * k + 1, 2.0, 0.0), (3 * k + 1, 3.0, -1e-30),
+                  (5 * k + 1, 5.0, -np.float32(2.0) ** -40)]
+    for n, s, o in cases:
+        got = bsi.bsi_general_grid_dims((n, 1, 1), (s, 1.0, 1.0), (o, 0.0, 0.0))[0]
+        assert got == general.grid_dims((n, 1, 1), (s, 1.0, 1.0), (o, 0.0, 0.0))[0], (n, s, o)

@@ -2,7 +2,7 @@
 
 Every volume's field and gradient must equal the per-volume launches bit for
 bit (same routines, schedule-independent arithmetic), under every schedule, in a
-direct launch and in repeated HIP-graph replays; two volumes are also checked
+direct launch and in repeated HIP-graph replays; every volume is also checked
 against the FP64 oracle on every element."""
 import json
 import os
@@ -96,22 +96,25 @@ def test_graph_replays(batch):
     plan.close()
 
 
-def test_two_volumes_against_oracle(batch):
+def test_every_volume_against_oracle(batch):
+    """All 32 volumes of the batched graph's workload against the FP64 oracle on
+    every voxel and every control point (the forward by the triple sum, the
+    adjoint by the per-point gather)."""
     dims, spac, vols, grids, dfields = batch
-    sizes = [int(np.prod(d)) for d in dims]
     plan = bsi.BatchPlan(dims, spac)
     f, g = _outputs(dims, spac)
     plan.bind(grids, f, dfields, g)
-    say("batch: oracle parity")
+    say("batch: oracle parity, 32 volumes")
     plan.run()
     torch.cuda.synchronize()
-    for i in np.argsort(sizes)[:2]:
-        d, s = tuple(dims[i]), tuple(spac[i])
+    for i in range(len(dims)):
+        d, s = tuple(int(v) for v in dims[i]), tuple(int(v) for v in spac[i])
         grid, dfield = vols[i]
         ref_f = oracle.forward(grid, d, s)
-        assert max_abs(host(f[i]), ref_f) <= 1e-5 * float(np.abs(grid).max())
-        ref_g = oracle.adjoint(dfield, d, s)
-        assert max_abs(host(g[i]), ref_g) <= 1e-5 * float(np.abs(ref_g).max())
+        assert max_abs(host(f[i]), ref_f) <= 1e-5 * float(np.abs(grid).max()), i
+        del ref_f
+        ref_g = oracle.adjoint_gather(dfield, d, s)
+        assert max_abs(host(g[i]), ref_g) <= 1e-5 * float(np.abs(ref_g).max()), i
     plan.close()
 
 
@@ -146,4 +149,43 @@ def test_forward_only_and_single_volume():
     plan.run()
     torch.cuda.synchronize()
     assert torch.equal(out, bsi.forward(grid, d, s))
+    plan.close()
+
+
+def test_bind_rejects_short_or_misshaped_lists():
+    """A list shorter than the plan, or a tensor of another volume's shape, raises
+    ValueError in the binding, before the library stores any pointer."""
+    say("batch: bind argument checks")
+    dims, spac = [(40, 30, 20), (33, 21, 17)], [(5, 5, 5), (4, 4, 4)]
+    plan = bsi.BatchPlan(dims, spac)
+    grids = [torch.zeros(bsi.grid_shape(d, s), device="cuda") for d, s in zip(dims, spac)]
+    fields = [torch.empty(bsi.field_shape(d), device="cuda") for d in dims]
+    with pytest.raises(ValueError):
+        plan.bind(grids[:1], fields[:1])
+    with pytest.raises(ValueError):
+        plan.bind(grids, fields[::-1])
+    with pytest.raises(ValueError):
+        plan.bind(grids, fields, dfields=[fields[0]], grid_grads=[grids[0]])
+    plan.bind(grids, fields)
+    plan.run()
+    torch.cuda.synchronize()
+    for g, f, d, s in zip(grids, fields, dims, spac):
+        assert torch.equal(f, bsi.forward(g, d, s))
+    plan.close()
+
+
+def test_invalid_forced_schedule_rejected(batch):
+    dims, spac, vols, grids, dfields = batch
+    say("batch: invalid BSI_FORCE_CONFIG")
+    plan = bsi.BatchPlan(dims[:2], spac[:2])
+    f, g = _outputs(dims[:2], spac[:2])
+    plan.bind(grids[:2], f, dfields[:2], g)
+    os.environ["BSI_FORCE_CONFIG"] = "999"
+    try:
+        with pytest.raises(bsi.BSIError):
+            plan.tune()
+        with pytest.raises(bsi.BSIError):
+            bsi.BatchPlan(dims[:2], spac[:2])
+    finally:
+        del os.environ["BSI_FORCE_CONFIG"]
     plan.close()
