@@ -477,6 +477,387 @@ __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, floa
   }
 }
 
+// ----------------------------------------------------------------------------
+// Pass 1, z-first ("column march").  A brick is kAdjZBX = 64 consecutive
+// x-voxels (one per lane) by kAdjZBY rows by a run of whole z-tiles.  Wave w of
+// the workgroup owns rows y0 + w R .. y0 + w R + R - 1 (R = kAdjZRows), so each
+// lane owns one voxel column per row and marches z.  Per voxel plane it loads
+// its R voxels (a wave reads 768 contiguous bytes per row, coalesced) and
+// accumulates the z-contraction of Eq. 1's transpose in registers,
+//   A_r[n] += Bz_n(w) * dfield[z][y_r][x]        (n = cz - tz, 4 planes),
+// the only per-voxel work.  When a z-tile ends, plane A[0] is finished for the
+// brick's voxel rows: it is contracted over x and y in LDS,
+//   H[y][cx]  = sum_x Bx_{cx - floor(x/dx)}(u(x)) A0[y][x]   (x ascending)
+//   G[cy][cx] = sum_y By_{cy - floor(y/dy)}(v(y)) H[y][cx]   (y ascending)
+// and G is written as the brick's partial gradient of that control plane.  The
+// x-contraction is per wave (its own rows, wave-private LDS); H is
+// double-buffered, so one workgroup barrier per finished plane orders the
+// x-contraction of plane k before the y-contraction of plane k, and the
+// y-contraction of plane k - 1 before the x-contraction of plane k + 1.
+// Pass 2 (unchanged) sums the partials of the bricks meeting each point.
+// ----------------------------------------------------------------------------
+#ifndef BSI_ADJZ_ROWS
+#define BSI_ADJZ_ROWS 2
+#endif
+#ifndef BSI_ADJZ_WAVES
+#define BSI_ADJZ_WAVES 8
+#endif
+#ifndef BSI_ADJZ_TARGET_Z
+#define BSI_ADJZ_TARGET_Z 48
+#endif
+constexpr int kAdjZRows = BSI_ADJZ_ROWS;              // rows per lane (R)
+constexpr int kAdjZWaves = BSI_ADJZ_WAVES;            // waves per workgroup
+constexpr int kAdjZThreads = kAdjZWaves * kWave;
+constexpr int kAdjZBX = kWave;                         // brick width (voxels)
+constexpr int kAdjZBY = kAdjZWaves * kAdjZRows;        // brick height (rows)
+constexpr int kAdjZTargetZ = BSI_ADJZ_TARGET_Z;        // brick depth bound (voxels, at least one tile)
+#ifndef BSI_ADJZ_WPE
+#define BSI_ADJZ_WPE 6
+#endif
+#ifndef BSI_ADJZ_AHEAD
+#define BSI_ADJZ_AHEAD 2
+#endif
+constexpr int kAdjZAhead = BSI_ADJZ_AHEAD;             // voxel planes of loads in flight per wave
+
+// Window columns of a brick of kAdjZBX voxels at x spacing dx (0: any spacing
+// above kAdjMaxDX): a run of w voxels meets at most (w - 1)/dx + 2 tiles, and
+// exactly w / dx when the run is whole tiles (spacing 1).
+__host__ __device__ constexpr int adjz_cx_max(int dx) {
+  return dx == 1 ? kAdjZBX + 3 : (kAdjZBX - 1) / (dx > 0 ? dx : kAdjMaxDX + 1) + 5;
+}
+constexpr int kAdjZCyMax = kAdjZBY + 3;  // window rows at spacing 1 (the most)
+// Finished partial planes are staged in LDS and stored in batches.  On this
+// chip loads and stores share one counter of outstanding memory operations,
+// and a store issued while loads are in flight makes the next wait for a load
+// wait for everything: a store per finished plane would drain the planes of
+// loads in flight at every z-tile.  With the partials of a whole brick staged
+// (spacings of 5 and more), they are stored once, after the brick's last load.
+#ifndef BSI_ADJZ_STAGE_FLOATS
+#define BSI_ADJZ_STAGE_FLOATS 6144
+#endif
+constexpr int kAdjZStageFloats = BSI_ADJZ_STAGE_FLOATS;  // 24 KB
+// The x-contraction of a finished plane runs on tile lanes (16 x-tiles per row
+// of 16 lanes) when a brick row holds at most 16 tiles: x spacing 4 (bricks
+// start on multiples of 64, so exactly 16 tiles), 5..12, and the generic path
+// (spacing 13 or more, at most 6 tiles).  Spacings 1..3 sum each column
+// directly (adjz_xsum).
+__host__ __device__ constexpr bool adjz_tile_lanes(int dx) { return dx == 0 || dx >= 4; }
+static_assert(kAdjTilesX == 16 && kWave / kAdjTilesX >= kAdjZRows, "a wave's rows fit its rows of 16 tile lanes");
+
+template <int DX>
+struct AdjZSmem {
+  float F[kAdjZWaves][kAdjZRows * kWave * 3];       // finished plane, this wave's rows (wave-private)
+  float H[2][kAdjZBY * adjz_cx_max(DX) * 3];         // x-contracted rows, double-buffered
+  float WYC[kAdjZCyMax * kAdjZBY];                  // By weight of brick row y for window row cy
+  int YR[kAdjZCyMax * 2];                           // rows [ya, yb) of the brick in cy's support
+  float P[kAdjZStageFloats];                        // finished partial planes awaiting their store
+};
+
+// Whether a brick's whole window of partials (cm_z planes of cm_y * cm_x
+// points) fits the LDS stage; otherwise each plane is stored as it is finished.
+__host__ __device__ inline bool adjz_stage_all(const AdjGeom& a) {
+  return (long)a.z.cm * a.y.cm * a.x.cm * 3 <= kAdjZStageFloats;
+}
+
+// Per-brick y tables: WYC[cyl][yl] = By weight of brick row yl for window row
+// cyl (0 outside cy's support), YR[cyl] = the support's rows within the brick.
+// Collective; a leading barrier keeps a previous brick's readers safe, and the
+// first finished plane's barrier orders these writes before any read.
+__device__ __forceinline__ void adjz_tables(const AdjGeom& a, const AdjBrick& b, const float* __restrict__ lut,
+                                            float* __restrict__ WYC, int* __restrict__ YR, int tid) {
+  const VolGeom& g = a.g;
+  __syncthreads();
+  for (int i = tid; i < b.Cy * kAdjZBY; i += kAdjZThreads) {
+    const int cyl = i / kAdjZBY, yl = i - cyl * kAdjZBY;
+    const int y = b.y0 + yl;
+    float wv = 0.f;
+    if (y < b.ye) {
+      const int t = y / g.dy;
+      const int m = b.cy0 + cyl - t;
+      if (m >= 0 && m < 4) wv = lut_row(lut, g.dy, y - t * g.dy)[m];
+    }
+    WYC[i] = wv;
+  }
+  for (int cyl = tid; cyl < b.Cy; cyl += kAdjZThreads) {
+    const int cy = b.cy0 + cyl;
+    YR[2 * cyl] = max(max(0, (cy - 3) * g.dy), b.y0) - b.y0;
+    YR[2 * cyl + 1] = max(min((cy + 1) * g.dy, b.ye) - b.y0, YR[2 * cyl]);
+  }
+}
+
+// Offsets (floats, within a voxel plane) of this lane's R voxels: row
+// y0 + wave R + r, column x0 + lane, both clamped into the brick so that every
+// lane loads from a valid address without a branch.  A clamped lane's values
+// are never read: the x-contraction reads only columns inside the brick and
+// the y-contraction only rows inside it.  A plane holds < 2^32 floats.
+template <int R>
+__host__ __device__ inline void adjz_offsets(const AdjBrick& b, int nx, int wave, int lane, uint32_t (&off)[R]) {
+  const int x = imin(b.x0 + lane, b.xe - 1);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int y = imin(b.y0 + wave * R + r, b.ye - 1);
+    off[r] = ((uint32_t)y * (uint32_t)nx + (uint32_t)x) * 3u;
+  }
+}
+
+// x-contraction of one window column cxl for brick row r of this wave:
+//   sum over voxels x of the brick in cx's support [(cx-3)dx, (cx+1)dx),
+//   ascending, of Bx_{cx - floor(x/dx)}(x - floor(x/dx) dx) * F[r][x - x0].
+template <int DX>
+__device__ __forceinline__ F3 adjz_xsum(const float* __restrict__ Fr, const AdjBrick& b, int dx, int cx,
+                                        const float* __restrict__ lut) {
+  F3 s{0.f, 0.f, 0.f};
+  if constexpr (DX > 0) {
+    // one tile at a time: its DX voxel loads in flight together, few registers
+    // (the emission runs while the z-accumulators and the next planes' loads
+    // are live)
+#pragma unroll 1
+    for (int j = 0; j < 4; ++j) {  // tile cx - 3 + j, weight index l = 3 - j
+      const int xt = (cx - 3 + j) * DX - b.x0;  // the tile's first voxel, brick-relative
+#pragma unroll
+      for (int o = 0; o < DX; ++o) {
+        const int xl = xt + o;
+        if (xl >= 0 && xl < b.xe - b.x0) {
+          const float w = lut_row(lut, DX, o)[3 - j];  // uniform: a scalar load
+          const float* q = Fr + xl * 3;
+          s.x = fmaf(w, q[0], s.x);
+          s.y = fmaf(w, q[1], s.y);
+          s.z = fmaf(w, q[2], s.z);
+        }
+      }
+    }
+  } else {
+    const int lo = imax((cx - 3) * dx, b.x0), hi = imin((cx + 1) * dx, b.xe);
+    for (int x = lo; x < hi; ++x) {
+      const int t = x / dx;
+      const float w = lut_row(lut, dx, x - t * dx)[cx - t];
+      const float* q = Fr + (x - b.x0) * 3;
+      s.x = fmaf(w, q[0], s.x);
+      s.y = fmaf(w, q[1], s.y);
+      s.z = fmaf(w, q[2], s.z);
+    }
+  }
+  return s;
+}
+
+// Values of the neighbouring lanes within a quad (DPP quad_perm): lane ^ 1 and
+// lane ^ 2.  After s += swap1(s) and then s += swap2(s), every lane of the quad
+// holds (l0 + l1) + (l2 + l3) with the same bits (addition is commutative).
+__device__ __forceinline__ float quad_swap1(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float quad_swap2(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, false));
+}
+
+// Finished control plane number k of the brick (czl = its window index).
+// Collective over the workgroup; f[r] is this lane's value of A0 for row r.
+template <int DX, bool StageAll>
+__device__ __forceinline__ void adjz_emit(const AdjGeom& a, const AdjBrick& b, float* __restrict__ pbase,
+                                          AdjZSmem<DX>& sm, const float* __restrict__ lut, int tid, int czl,
+                                          bool last, const F3 (&f)[kAdjZRows]) {
+  constexpr int CXM = adjz_cx_max(DX);
+  const int lane = tid & (kWave - 1), wave = tid / kWave;
+  const int dx = DX > 0 ? DX : a.g.dx;
+  float* Fw = sm.F[wave];
+  wave_lds_sync();  // this wave's x-contraction of the previous plane is done with Fw
+#pragma unroll
+  for (int r = 0; r < kAdjZRows; ++r) stf3(Fw + (r * kWave + lane) * 3, f[r]);
+  wave_lds_sync();
+  float* H = sm.H[czl & 1];  // czl counts the brick's finished planes
+  const int nrow = b.ye - b.y0 - wave * kAdjZRows;  // this wave's rows inside the brick
+  if constexpr (adjz_tile_lanes(DX)) {
+    // Tile lanes: lane (rr, t) = (lane / 16, lane % 16) forms the x-moments of
+    // tile cx0 + t in row rr of this wave,
+    //   M_l = sum_o Bx_l(o) F[rr][t dx + o - x0]    (o ascending, voxels in the brick)
+    // each voxel read once; the 16 lanes of a row then finish the columns with
+    // row rotations (adj_xcombine): column t and, for t < 3, column 16 + t.
+    const int rr = lane / kAdjTilesX, t = lane % kAdjTilesX;
+    const bool act = rr < kAdjZRows && rr < nrow && t < b.ntx;
+    F3 M[4];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) M[l] = F3{0.f, 0.f, 0.f};
+    if (act) {
+      const int xt = (b.cx0 + t) * dx - b.x0;  // the tile's first voxel, brick-relative (may be < 0)
+      const float* Fr = Fw + rr * kWave * 3;
+      const int nxb = b.xe - b.x0;
+      auto voxel = [&](int o) {
+        const int xl = xt + o;
+        if (xl >= 0 && xl < nxb) {
+          const float* w = lut_row(lut, dx, o);
+          const F3 v = ldf3(Fr + xl * 3);
+#pragma unroll
+          for (int l = 0; l < 4; ++l) {
+            M[l].x = fmaf(w[l], v.x, M[l].x);
+            M[l].y = fmaf(w[l], v.y, M[l].y);
+            M[l].z = fmaf(w[l], v.z, M[l].z);
+          }
+        }
+      };
+      // pairs of voxels in flight: few registers while the z-accumulators and
+      // the next planes' loads are live
+#pragma unroll 1
+      for (int o = 0; o < dx; o += 2) {
+        voxel(o);
+        if (o + 1 < dx) voxel(o + 1);
+      }
+    }
+    F3 cm, cw;
+    adj_xcombine(t, M, cm, cw);  // every lane of the wave takes part
+    if (rr < kAdjZRows && rr < nrow) {
+      float* hrow = H + (wave * kAdjZRows + rr) * CXM * 3;
+      if (t < b.Cx) stf3(hrow + t * 3, cm);
+      if (t < 3 && kAdjTilesX + t < b.Cx) stf3(hrow + (kAdjTilesX + t) * 3, cw);
+    }
+  } else {
+    const int items = imin(nrow, kAdjZRows) * b.Cx;
+    for (int it = lane; it < items; it += kWave) {
+      const int r = it / b.Cx, cxl = it - r * b.Cx;
+      stf3(H + ((wave * kAdjZRows + r) * CXM + cxl) * 3, adjz_xsum<DX>(Fw + r * kWave * 3, b, dx, b.cx0 + cxl, lut));
+    }
+  }
+  __syncthreads();
+  // y-contraction: wave w takes window rows cyl = w, w + kAdjZWaves, ...;
+  // lane j takes columns cxl = j, j + 64, ...  Every row y of cy's support
+  // inside the brick is summed in ascending order with its By weight, which
+  // is the same for the whole wave (a scalar load of the basis table).
+  {
+    const VolGeom& g = a.g;
+    for (int cyl = wave; cyl < b.Cy; cyl += kAdjZWaves) {
+      const int cy = b.cy0 + cyl;
+      const int ya = imax(imax(0, (cy - 3) * g.dy), b.y0), yb = imin((cy + 1) * g.dy, b.ye);
+      for (int cxl = lane; cxl < b.Cx; cxl += kWave) {
+        const float* hp = H + cxl * 3;
+        float ax = 0.f, ay = 0.f, az = 0.f;
+        // tiles t of the support, ascending; rows y of each with offset y - t dy
+        int t = ya / g.dy, oy = ya - t * g.dy;
+#pragma unroll 1
+        for (int y = ya; y < yb; ++y) {
+          const float wv = lut_row(lut, g.dy, oy)[cy - t];
+          const float* hq = hp + (y - b.y0) * CXM * 3;
+          ax = fmaf(wv, hq[0], ax);
+          ay = fmaf(wv, hq[1], ay);
+          az = fmaf(wv, hq[2], az);
+          if (++oy == g.dy) {
+            oy = 0;
+            ++t;
+          }
+        }
+        if constexpr (StageAll)
+          stf3(sm.P + adj_part_offset(a, czl, cyl, cxl), F3{ax, ay, az});
+        else
+          stf3(pbase + adj_part_offset(a, czl, cyl, cxl), F3{ax, ay, az});
+      }
+    }
+  }
+  // After the brick's last plane (its loads all done), the staged window goes
+  // out as one contiguous run of whole (padded) planes.  A following brick of
+  // this workgroup writes the stage only after adjz_tables' barrier.
+  if constexpr (StageAll) {
+    if (last) {
+      __syncthreads();
+      const int n = (czl + 1) * a.y.cm * a.x.cm;
+      for (int i = tid; i < n; i += kAdjZThreads) stf3(pbase + i * 3, ldf3(sm.P + i * 3));
+    }
+  }
+}
+
+template <bool Stream>
+__device__ __forceinline__ void adjz_load(const float* __restrict__ plane, const uint32_t (&off)[kAdjZRows],
+                                          F3 (&d)[kAdjZRows]) {
+#pragma unroll
+  for (int r = 0; r < kAdjZRows; ++r) d[r] = ldf3_dfield<Stream>(plane + off[r]);
+}
+
+// Pass 1 for one brick, z-first.  Collective over the workgroup (kAdjZThreads
+// threads).  Stream: dfield is read with non-temporal loads.
+template <int DX, bool Stream = true, bool StageAll = false>
+__device__ __forceinline__ void adjz_brick(const float* __restrict__ dfield, float* __restrict__ part,
+                                           const AdjGeom& a, const float* __restrict__ lut, int brick,
+                                           AdjZSmem<DX>& sm, int tid) {
+  constexpr int R = kAdjZRows;
+  const VolGeom& g = a.g;
+  const AdjBrick b = adj_brick_geom(a, brick);
+  float* pbase = part + (size_t)brick * adj_brick_stride(a);
+  adjz_tables(a, b, lut, sm.WYC, sm.YR, tid);
+
+  const int lane = tid & (kWave - 1), wave = uniform(tid / kWave);
+  uint32_t off[R];
+  adjz_offsets<R>(b, g.nx, wave, lane, off);
+  const size_t zs = (size_t)g.ny * g.nx * 3;
+  const float* plane0 = dfield + (size_t)b.z0 * zs;
+  auto plane = [&](int z) { return plane0 + (size_t)(z - b.z0) * zs; };
+
+  F3 acc[R][4];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int n = 0; n < 4; ++n) acc[r][n] = F3{0.f, 0.f, 0.f};
+  int tz = b.cz0;        // z-bricks are whole tiles: b.z0 = tz * dz
+  int oz = 0;
+  auto emit0 = [&](int czl, bool last) {
+    F3 f[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) f[r] = acc[r][0];
+    adjz_emit<DX, StageAll>(a, b, pbase, sm, lut, tid, czl, last, f);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+      for (int n = 0; n < 3; ++n) acc[r][n] = acc[r][n + 1];
+      acc[r][3] = F3{0.f, 0.f, 0.f};
+    }
+  };
+  // One voxel plane: z-accumulation, then the loads of the plane kAdjZAhead
+  // planes ahead into the same registers (when that plane exists: Load), then
+  // the emission when a z-tile ends.
+  const float* ahead = nullptr;  // the plane kAdjZAhead ahead of the one consumed next
+  auto consume = [&](F3 (&d)[R], int z, bool load) {
+    const float* wz = lut_row(lut, g.dz, oz);
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      const float w = wz[n];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        acc[r][n].x = fmaf(w, d[r].x, acc[r][n].x);
+        acc[r][n].y = fmaf(w, d[r].y, acc[r][n].y);
+        acc[r][n].z = fmaf(w, d[r].z, acc[r][n].z);
+      }
+    }
+    if (load) adjz_load<Stream>(ahead, off, d);
+    ahead += zs;  // plane z + 1 + kAdjZAhead
+    if (++oz == g.dz && z + 1 < b.ze) {
+      emit0(tz - b.cz0, false);
+      oz = 0;
+      ++tz;
+    }
+  };
+  // kAdjZAhead register sets, each holding one plane's loads.  The loop is
+  // unrolled over them, and its main part runs only while every plane of the
+  // group and every plane kAdjZAhead ahead exists, so its loads are
+  // unconditional: each set keeps fixed registers, and waiting for one set's
+  // loads leaves the other sets' loads in flight.
+  // (The first sets are loaded unconditionally, from the brick's last plane
+  // when it is shallower, so the loop is entered with the same loads in flight
+  // on every path and its waits count them exactly.)
+  F3 d[kAdjZAhead][R];
+#pragma unroll
+  for (int j = 0; j < kAdjZAhead; ++j) adjz_load<Stream>(plane(imin(b.z0 + j, b.ze - 1)), off, d[j]);
+  ahead = plane0 + (size_t)kAdjZAhead * zs;
+  int z = b.z0;
+  for (; z + 2 * kAdjZAhead <= b.ze; z += kAdjZAhead) {
+#pragma unroll
+    for (int j = 0; j < kAdjZAhead; ++j) consume(d[j], z + j, true);
+  }
+  for (; z < b.ze; z += kAdjZAhead) {
+#pragma unroll
+    for (int j = 0; j < kAdjZAhead; ++j)
+      if (z + j < b.ze) consume(d[j], z + j, z + j + kAdjZAhead < b.ze);
+  }
+  // the last tile's four planes (the last three are shared with the next brick)
+#pragma unroll 1
+  for (int n = 0; n < 4; ++n) emit0(tz - b.cz0 + n, n == 3);
+}
+
 // Pass 2 for one control point (cx, cy, cz): fixed-order sum of brick partials.
 // Bricks whose voxels meet the point's support [(c-3)d, (c+1)d) on each axis,
 // summed bz, then by, then bx ascending.  When no axis has more than two such

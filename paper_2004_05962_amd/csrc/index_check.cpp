@@ -31,51 +31,42 @@ struct Check {
     if (!(c)) return ck.fail(std::string(what) + " [" #c "]");                   \
   } while (0)
 
-template <int DX>
-bool check_plane_offsets(const AdjGeom& a, const AdjBrick& b, Check& ck) {
+// Loads and LDS indices of the z-first pass 1 (adjz_brick) for one brick.
+bool check_adjz_brick(const AdjGeom& a, const AdjBrick& b, Check& ck) {
   const size_t plane = (size_t)a.g.nx * a.g.ny * 3;
-  for (int w = 0; w < kAdjWaves; ++w)
+  REQUIRE(b.z0 == b.cz0 * a.g.dz, "z-bricks start on tile boundaries (the march starts at offset 0)");
+  REQUIRE(b.xe - b.x0 <= kAdjZBX && b.ye - b.y0 <= kAdjZBY, "brick within one lane per voxel and row");
+  const int dxc = a.g.dx <= kAdjMaxDX ? a.g.dx : 0;
+  REQUIRE(b.Cx <= adjz_cx_max(dxc), "x window within the H buffer's row");
+  REQUIRE(b.Cy <= kAdjZCyMax, "y window within the y tables");
+  for (int w = 0; w < kAdjZWaves; ++w)
     for (int lane = 0; lane < kWave; ++lane) {
-      uint32_t off[DX];
-      adj_plane_offsets<DX>(b, a.g.nx, b.y0 + w * kAdjRowsPerWave, lane, off);
-      for (int k = 0; k < DX; ++k) {
-        REQUIRE((size_t)off[k] + 3 <= plane, "pass-1 load outside its voxel plane");
-        const int x = (int)(off[k] / 3 % a.g.nx), y = (int)(off[k] / 3 / a.g.nx);
+      uint32_t off[kAdjZRows];
+      adjz_offsets<kAdjZRows>(b, a.g.nx, w, lane, off);
+      for (int r = 0; r < kAdjZRows; ++r) {
+        REQUIRE((size_t)off[r] + 3 <= plane, "pass-1 load outside its voxel plane");
+        const int x = (int)(off[r] / 3 % a.g.nx), y = (int)(off[r] / 3 / a.g.nx);
         REQUIRE(x >= b.x0 && x < b.xe && y >= b.y0 && y < b.ye, "pass-1 load outside its brick");
       }
     }
   return true;
 }
 
-bool check_loads(const AdjGeom& a, const AdjBrick& b, Check& ck) {
-  switch (a.g.dx) {
-    case 1: return check_plane_offsets<1>(a, b, ck);
-    case 2: return check_plane_offsets<2>(a, b, ck);
-    case 3: return check_plane_offsets<3>(a, b, ck);
-    case 4: return check_plane_offsets<4>(a, b, ck);
-    case 5: return check_plane_offsets<5>(a, b, ck);
-    case 6: return check_plane_offsets<6>(a, b, ck);
-    case 7: return check_plane_offsets<7>(a, b, ck);
-    case 8: return check_plane_offsets<8>(a, b, ck);
-    case 9: return check_plane_offsets<9>(a, b, ck);
-    case 10: return check_plane_offsets<10>(a, b, ck);
-    case 11: return check_plane_offsets<11>(a, b, ck);
-    case 12: return check_plane_offsets<12>(a, b, ck);
-    default: {
-      // generic path: each active lane reads its tile row's nval voxels directly
-      for (int tid = 0; tid < kAdjThreads; ++tid) {
-        const int txl = tid % kAdjTilesX, y = b.y0 + tid / kAdjTilesX, x = (b.cx0 + txl) * a.g.dx;
-        if (txl < b.ntx && y < b.ye) REQUIRE(x >= b.x0 && imin(a.g.dx, a.g.nx - x) + x <= b.xe, "generic load");
-      }
-      return true;
-    }
-  }
+// Brick geometry of the fused step's pass 1 (x-tile lanes, fused_brick).
+bool check_fused_brick(const AdjGeom& a, const AdjBrick& b, Check& ck) {
+  REQUIRE(b.ntx >= 1 && b.ntx <= kAdjTilesX, "x-tiles per brick (one lane each)");
+  REQUIRE(b.ye - b.y0 <= kAdjMaxY, "rows per brick (one lane row each)");
+  REQUIRE(b.x0 == b.cx0 * a.g.dx, "x-bricks start on tile boundaries");
+  REQUIRE(b.Cx <= kAdjMaxCx, "x window (LDS slot)");
+  REQUIRE(b.Cy <= kAdjMaxCy, "y window (LDS tables)");
+  return true;
 }
 
-// Pass 1 and pass 2 of the adjoint for one geometry.
-bool check_adjoint(const VolGeom& g, Check& ck) {
-  static_assert(kAdjMaxDX == 12, "one case per specialised spacing");
-  const AdjGeom a = make_adj_geom(g);
+// Pass 1 (its bricks, via `brick_check`) and pass 2 of a two-pass adjoint with
+// brick geometry `a`.
+template <class BrickCheck>
+bool check_adjoint(const AdjGeom& a, BrickCheck brick_check, Check& ck) {
+  const VolGeom& g = a.g;
   const size_t ws = adj_workspace_bytes(a) / sizeof(float);
   const int nb = a.x.nb * a.y.nb * a.z.nb;
   REQUIRE(a.x.nb >= 1 && a.y.nb >= 1 && a.z.nb >= 1, "brick counts");
@@ -88,11 +79,8 @@ bool check_adjoint(const VolGeom& g, Check& ck) {
     REQUIRE(0 <= b.x0 && b.x0 < b.xe && b.xe <= g.nx, "brick x range");
     REQUIRE(0 <= b.y0 && b.y0 < b.ye && b.ye <= g.ny, "brick y range");
     REQUIRE(0 <= b.z0 && b.z0 < b.ze && b.ze <= g.nz, "brick z range");
-    REQUIRE(b.ntx >= 1 && b.ntx <= kAdjTilesX, "x-tiles per brick (one lane each)");
-    REQUIRE(b.ye - b.y0 <= kAdjMaxY, "rows per brick (one lane row each)");
-    REQUIRE(b.x0 == b.cx0 * g.dx, "x-bricks start on tile boundaries");
-    REQUIRE(b.Cx <= a.x.cm && b.Cx <= kAdjMaxCx, "x window (partials stride, LDS slot)");
-    REQUIRE(b.Cy <= a.y.cm && b.Cy <= kAdjMaxCy, "y window (partials stride, LDS tables)");
+    REQUIRE(b.Cx <= a.x.cm, "x window (partials stride)");
+    REQUIRE(b.Cy <= a.y.cm, "y window (partials stride)");
     const int cz = adj_brick_cz(a, b);
     REQUIRE(cz <= a.z.cm, "z window (partials stride)");
     REQUIRE(b.cx0 + b.Cx <= g.gx && b.cy0 + b.Cy <= g.gy && b.cz0 + cz <= g.gz, "window inside the grid");
@@ -101,7 +89,7 @@ bool check_adjoint(const VolGeom& g, Check& ck) {
     REQUIRE(b.cz0 == adj_brick_c0(a.z, id / (a.x.nb * a.y.nb), g.dz), "z window start");
     const size_t last = (size_t)id * adj_brick_stride(a) + adj_part_offset(a, cz - 1, b.Cy - 1, b.Cx - 1);
     REQUIRE(last + 3 <= ws, "partial store outside the workspace");
-    if (!check_loads(a, b, ck)) return false;
+    if (!brick_check(a, b, ck)) return false;
     Cx[id] = b.Cx;
     Cy[id] = b.Cy;
     Cz[id] = cz;
@@ -143,6 +131,11 @@ bool check_adjoint(const VolGeom& g, Check& ck) {
             }
       }
   return true;
+}
+
+bool check_adjoints(const VolGeom& g, Check& ck) {
+  return check_adjoint(make_adj_geom(g), check_adjz_brick, ck) &&
+         check_adjoint(make_fused_geom(g), check_fused_brick, ck);
 }
 
 // The marching forward (fwd_block) with workgroup shape T and C components.
@@ -216,7 +209,7 @@ int bsi_check_indices(const int32_t dims[3], const int32_t spacing[3], char* msg
     return -1;
   }
   Check ck;
-  check_adjoint(g, ck) && check_forward(g, ck);
+  check_adjoints(g, ck) && check_forward(g, ck);
   std::snprintf(msg, msglen, "%s", ck.msg.c_str());
   return ck.ok ? 0 : 1;
 }
