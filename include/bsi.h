@@ -143,7 +143,8 @@ int32_t bsi_adjoint_reduce(const void* workspace, size_t workspace_bytes,
  * origin[a] = o, -s < o <= 0 (host float arrays):
  *   control point (storage index) c sits at voxel o + (c - 1) s;
  *   voxel x reads c = i .. i+3, i = floor(t), weights B_l(t - i), t = (x - o)/s,
- *   with t formed in FP64 from the float values of s and o;
+ *   where i is the exact floor of (x - o)/s for the float values of s and o
+ *   (decided with FP32 error-free arithmetic) and t - i and the weights are FP32;
  *   the grid has g = floor((n - 1 - o)/s) + 4 points (ceil(n/s) + 3 for
  *   integer s and o = 0, where these calls compute the same map as
  *   bsi_forward / bsi_adjoint, up to FP32 rounding).

@@ -378,7 +378,7 @@ int32_t bsi_ssd_fused_workspace_size(const int32_t dims[3], const int32_t spacin
   VolGeom g;
   int32_t rc = make_geom(dims, spacing, &g);
   if (rc) return rc;
-  *bytes = fused_workspace_bytes(make_fused_geom(g));
+  *bytes = fused_workspace_bytes(make_adj_geom(g));
   return BSI_OK;
 }
 
@@ -395,7 +395,7 @@ int32_t bsi_ssd_fused(const float* grid, const float* moving, const float* fixed
   if (!grid_grad) return null_arg("grid_grad");
   if (!loss) return null_arg("loss");
   if (!workspace) return null_arg("workspace");
-  const AdjGeom a = make_fused_geom(g);
+  const AdjGeom a = make_adj_geom(g);
   const size_t need = fused_workspace_bytes(a);
   if (workspace_bytes < need) {
     set_error("workspace too small: need " + std::to_string(need) + " bytes");

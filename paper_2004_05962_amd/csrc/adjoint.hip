@@ -6,17 +6,16 @@
 namespace bsi {
 
 template <int DX>
-__global__ __launch_bounds__(kAdjZThreads) __attribute__((amdgpu_waves_per_eu(BSI_ADJZ_WPE))) void adj_pass1_kernel(const float* __restrict__ dfield,
-                                                                  float* __restrict__ part, AdjGeom a,
-                                                                  const float* __restrict__ lut) {
-  __shared__ AdjZSmem<DX> sm;
+__global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(BSI_ADJ_WPE))) void adj_pass1_kernel(
+    const float* __restrict__ dfield, float* __restrict__ part, AdjGeom a, const float* __restrict__ lut) {
+  __shared__ AdjSmem<DX> sm;
   const int nbricks = a.x.nb * a.y.nb * a.z.nb;
   const int brick = xcd_remap(blockIdx.x, gridDim.x);
   if (brick >= nbricks) return;  // uniform over the workgroup
-  if (adjz_stage_all(a))  // uniform: a function of the geometry
-    adjz_brick<DX, true, true>(dfield, part, a, lut, brick, sm, threadIdx.x);
+  if (adj_stage_all(a))  // uniform: a function of the geometry
+    adj_brick<DX, true, true>(dfield, part, a, lut, brick, sm, threadIdx.x);
   else
-    adjz_brick<DX, true, false>(dfield, part, a, lut, brick, sm, threadIdx.x);
+    adj_brick<DX, true, false>(dfield, part, a, lut, brick, sm, threadIdx.x);
 }
 
 constexpr int kGatherThreads = 256;
@@ -49,29 +48,13 @@ AdjAxis make_axis(int n, int d, int u, int k) {
 }
 }  // namespace
 
-// Bricks of the z-first pass 1: kAdjZBX voxels (one per lane) by kAdjZBY rows
-// by whole z-tiles, about kAdjZTargetZ planes deep (at least one tile).
+// Bricks of pass 1: kAdjBX voxels (one per lane) by kAdjBY rows by whole
+// z-tiles, about kAdjTargetZ planes deep (at least one tile).
 AdjGeom make_adj_geom(const VolGeom& g) {
   AdjGeom a;
   a.g = g;
-  a.x = make_axis(g.nx, g.dx, 1, kAdjZBX);
-  a.y = make_axis(g.ny, g.dy, 1, kAdjZBY);
-  const int kz = kAdjZTargetZ / g.dz > 0 ? kAdjZTargetZ / g.dz : 1;
-  a.z = make_axis(g.nz, g.dz, g.dz, kz);
-  return a;
-}
-
-// Bricks of the fused step's pass 1 (x-tile lanes, fused.hip).
-AdjGeom make_fused_geom(const VolGeom& g) {
-  AdjGeom a;
-  a.g = g;
-  // x: kAdjTilesX whole tiles per brick (one per lane of a row)
-  a.x = make_axis(g.nx, g.dx, g.dx, kAdjTilesX);
-  // y: whole tiles (single rows when a tile is taller than kAdjMaxY), at most
-  // kAdjMaxY rows per brick
-  const int uy = g.dy <= kAdjMaxY ? g.dy : 1;
-  a.y = make_axis(g.ny, g.dy, uy, kAdjMaxY / uy);
-  // z: whole tiles, about kAdjTargetZ voxels deep (at least one tile)
+  a.x = make_axis(g.nx, g.dx, 1, kAdjBX);
+  a.y = make_axis(g.ny, g.dy, 1, kAdjBY);
   const int kz = kAdjTargetZ / g.dz > 0 ? kAdjTargetZ / g.dz : 1;
   a.z = make_axis(g.nz, g.dz, g.dz, kz);
   return a;
@@ -84,7 +67,7 @@ size_t adj_workspace_bytes(const AdjGeom& a) {
 hipError_t launch_adjoint_partials(const float* dfield, const AdjGeom& a, const float* lut, float* part,
                                   hipStream_t s) {
   const long nbricks = (long)a.x.nb * a.y.nb * a.z.nb;
-  const dim3 grid((unsigned)nbricks), block(kAdjZThreads);
+  const dim3 grid((unsigned)nbricks), block(kAdjThreads);
   static_assert(kAdjMaxDX == 12, "one case per specialised spacing");
   switch (a.g.dx) {
     case 1: hipLaunchKernelGGL(adj_pass1_kernel<1>, grid, block, 0, s, dfield, part, a, lut); break;

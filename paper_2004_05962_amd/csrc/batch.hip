@@ -129,10 +129,10 @@ __global__ __launch_bounds__(kFwdThreads) void batch_fwd_kernel(const VolDesc* _
 // the generic path), each class with its own descriptor sub-table, so every
 // launch keeps the register footprint of its own specialisation.
 template <int DX>
-__global__ __launch_bounds__(kAdjZThreads) void batch_adj1_kernel(const VolDesc* __restrict__ vols, int count,
+__global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(BSI_ADJ_WPE))) void batch_adj1_kernel(const VolDesc* __restrict__ vols, int count,
                                                                    int64_t total, int chunked,
                                                                    const float* __restrict__ lut) {
-  __shared__ AdjZSmem<DX> sm;
+  __shared__ AdjSmem<DX> sm;
   const Slice s = make_slice(total, chunked);
   for (int64_t item = s.begin; item < s.end; item += s.step) {
     const int vi = uniform(find_volume(vols, count, item, kAdj1));
@@ -141,10 +141,10 @@ __global__ __launch_bounds__(kAdjZThreads) void batch_adj1_kernel(const VolDesc*
     // ordinary loads: with the forward running beside pass 1 in the graph,
     // streaming loads measured 2-5% slower here
     const int brick = (int)(item - d.first[kAdj1]);
-    if (adjz_stage_all(a))
-      adjz_brick<DX, false, true>(d.dfield, d.part, a, lut, brick, sm, threadIdx.x);
+    if (adj_stage_all(a))
+      adj_brick<DX, false, true>(d.dfield, d.part, a, lut, brick, sm, threadIdx.x);
     else
-      adjz_brick<DX, false, false>(d.dfield, d.part, a, lut, brick, sm, threadIdx.x);
+      adj_brick<DX, false, false>(d.dfield, d.part, a, lut, brick, sm, threadIdx.x);
   }
 }
 
@@ -259,7 +259,7 @@ hipError_t launch_adj1_class(bsi_batch* p, int c, hipStream_t s) {
   const int per_cu = sc.adj_per_cu;
   const int chunked = per_cu == 0 ? 0 : sc.chunked;
   const int64_t cg = per_cu == 0 ? ct : std::min<int64_t>(ct, (int64_t)per_cu * p->cus);
-  const dim3 gd((unsigned)cg), bd(kAdjZThreads);
+  const dim3 gd((unsigned)cg), bd(kAdjThreads);
   const VolDesc* v = p->d_cls + p->cls_first[c];
   static_assert(kAdjMaxDX == 12, "one case per specialised spacing");
   switch (c) {

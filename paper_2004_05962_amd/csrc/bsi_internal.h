@@ -28,7 +28,6 @@ int32_t lerp_lut_device_ptr(int dev, const float** out);
 int32_t make_geom(const int32_t dims[3], const int32_t spacing[3], VolGeom* g);
 int32_t check_control_plane(int32_t gx, int32_t gy);  // UNSUPPORTED at 2^31 floats or more
 AdjGeom make_adj_geom(const VolGeom& g);
-AdjGeom make_fused_geom(const VolGeom& g);  // the fused step's bricks (fused.hip)
 size_t adj_workspace_bytes(const AdjGeom& a);
 
 // Forward launch shape (workgroups of kFwdRows waves; z split into chunks).

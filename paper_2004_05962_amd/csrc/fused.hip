@@ -8,27 +8,20 @@
 //   L         = sum_x (W(x) - fixed(x))^2
 //   dL/dphi   = B^T [ 2 (W - fixed) dW/dp ]                    (the adjoint)
 //
-// Pass 1 keeps the adjoint's decomposition (adjoint_device.h): one workgroup
-// per brick, each thread one x-tile row marching z, the 16 lanes of a row
-// holding the brick's 16 x-tiles.  Per thread, T is evaluated sum-factorised:
-//   R_n(c)  = sum_m By_m(v) phi[tz+n][ty+m][c]   for the thread's own control
-//             column c (and column c + 16 for lanes < 3), control planes
-//             tz..tz+3 kept in a rolling window, one new plane per z-tile;
-//   P(c)    = sum_n Bz_n(w) R_n(c)               once per voxel plane;
-//   T(o)    = sum_l Bx_l(o) P(tx + l)            per voxel.
-// For spacings up to kFusedMaxDX the per-voxel work runs in voxel layout: each
-// wave publishes its rows' P in LDS, every lane takes voxels k * 64 + lane of
-// the wave's 4 rows (consecutive lanes on consecutive voxels, so the image
-// loads coalesce), evaluates T, samples the moving image and writes the
-// voxel's gradient 2 (W - fixed) dW/dp into the wave's transpose buffer, from
-// which the tile lanes read their rows: from there on it is the adjoint's
-// pass 1 with this gradient in place of dfield.  Larger spacings do the same
-// per tile lane, the three neighbouring columns of P taken from the row's
-// other lanes (DPP).
-// Each workgroup also sums its voxels' squared residuals in a fixed order into
-// one loss partial; pass 2 is the adjoint's fixed-order gather, and the loss is
-// the fixed-order sum of the partials.  No atomics: the bits depend on the
-// inputs only.
+// Pass 1 is the adjoint's z-first pass 1 (adjoint_device.h: the same bricks,
+// lanes, z-accumulation and emission) with dfield replaced by the voxel's
+// SSD gradient, computed on the spot.  T is evaluated as the forward kernel
+// does (fwd_block): per control plane, Q = sum_m By_m sum_l Bx_l phi from the
+// plane's window staged in LDS, kept for the 4 planes of the current z-tile,
+// and T = sum_n Bz_n Q per voxel plane, with the same operations in the same
+// order; the sampling and gradient are the SSD kernel's.  So the field, the
+// per-voxel gradient and the adjoint's accumulation are bit-identical to the
+// separate forward, SSD and adjoint kernels, and so is the control-grid
+// gradient; only the loss is summed in another order.
+//
+// Each workgroup sums its voxels' squared residuals in a fixed order into one
+// loss partial per brick; pass 2 is the adjoint's fixed-order gather, and the
+// loss is the fixed-order sum of the partials.  No atomics.
 #include "adjoint_device.h"
 #include "bsi_internal.h"
 #include "warp_device.h"
@@ -37,231 +30,245 @@ namespace bsi {
 
 namespace {
 
-// Spacings that take the warp in voxel layout (below); larger ones evaluate it
-// in tile layout.
-constexpr int kFusedMaxDX = 8;
-constexpr int kFusedCols = kAdjTilesX + 3;  // window columns of one brick row
+// The fused pass uses the adjoint's bricks with one row per lane: kAdjBY
+// waves of 64 lanes, so each lane keeps the forward's 4 contracted planes and
+// the adjoint's 4 accumulators for a single voxel column.
+constexpr int kFusedWaves = kAdjBY;
+constexpr int kFusedThreads = kFusedWaves * kWave;
 
-__host__ __device__ constexpr bool fused_voxel_layout(int dx) { return dx >= 1 && dx <= kFusedMaxDX; }
+// A staged control plane: the brick's window of at most kAdjBY + 3 rows by
+// adj_cx_max(DX) columns (pitch adj_cx_max(DX) points).
+template <int DX>
+__host__ __device__ constexpr int fused_slot_floats() {
+  return (kAdjBY + 3) * adj_cx_max(DX) * 3;
+}
+template <int DX>
+__host__ __device__ constexpr int fused_loads() {  // staged floats per thread
+  return (fused_slot_floats<DX>() + kFusedThreads - 1) / kFusedThreads;
+}
 
 template <int DX>
 struct FusedSmem {
-  AdjEmitSmem e;
-  float red[kAdjThreads];
-  // per wave: column values P of its 4 rows, and the transpose buffer that
-  // carries each voxel's gradient from voxel lanes to tile lanes
-  float P[fused_voxel_layout(DX) ? kAdjWaves * kAdjRowsPerWave * kFusedCols * 3 : 1];
-  float T[fused_voxel_layout(DX) ? kAdjWaves * adj_wave_buf(DX) : 1];
-  float wx[fused_voxel_layout(DX) ? 4 * DX : 1];  // x weights of the offsets 0..DX-1
+  AdjSmem<DX> adj;
+  float ring[2][fused_slot_floats<DX>()];
+  float red[kFusedThreads];
 };
 
-// Value of lane (i + L) mod 16 of this lane's row of 16 lanes.
-template <int L>
-__device__ __forceinline__ F3 row_from_right(const F3& v) {
-  return F3{row_ror<kAdjTilesX - L>(v.x), row_ror<kAdjTilesX - L>(v.y), row_ror<kAdjTilesX - L>(v.z)};
-}
+// Loads of control plane cz's window into registers (thread tid takes floats
+// e = tid + k kFusedThreads of the Cy x Cx x 3 window), and their store into a
+// slot with row pitch adj_cx_max(DX) points.
+template <int DX>
+struct FusedStage {
+  int src[fused_loads<DX>()];  // float offset within a control plane, -1 outside the window
+  int dst[fused_loads<DX>()];
+};
 
-template <int L>
-__device__ __forceinline__ F3 column_right(int txl, const F3& pm, const F3& pw) {
-  const F3 m = row_from_right<L>(pm), w = row_from_right<L>(pw);
-  return txl + L < kAdjTilesX ? m : w;
-}
-
-__device__ __forceinline__ F3 zcombine(const float* __restrict__ wz, const F3 (&R)[4]) {
-  F3 p;
-  p.x = fmaf(wz[3], R[3].x, fmaf(wz[2], R[2].x, fmaf(wz[1], R[1].x, wz[0] * R[0].x)));
-  p.y = fmaf(wz[3], R[3].y, fmaf(wz[2], R[2].y, fmaf(wz[1], R[1].y, wz[0] * R[0].y)));
-  p.z = fmaf(wz[3], R[3].z, fmaf(wz[2], R[2].z, fmaf(wz[1], R[1].z, wz[0] * R[0].z)));
-  return p;
+template <int DX>
+__device__ __forceinline__ FusedStage<DX> fused_stage_map(const VolGeom& g, const AdjBrick& b, int tid) {
+  constexpr int CXM = adj_cx_max(DX);
+  FusedStage<DX> m;
+  const int wrow = b.Cx * 3;
+#pragma unroll
+  for (int k = 0; k < fused_loads<DX>(); ++k) {
+    const int e = tid + k * kFusedThreads;
+    const int cyl = e / wrow, i = e - cyl * wrow;
+    const bool in = cyl < b.Cy;
+    m.src[k] = in ? ((b.cy0 + cyl) * g.gx + b.cx0) * 3 + i : -1;
+    m.dst[k] = cyl * CXM * 3 + i;
+  }
+  return m;
 }
 
 template <int DX>
+__device__ __forceinline__ void fused_fetch(const float* __restrict__ grid, const VolGeom& g, const FusedStage<DX>& m,
+                                            int cz, float (&r)[fused_loads<DX>()]) {
+  const float* plane = grid + (size_t)cz * g.gy * g.gx * 3;
+#pragma unroll
+  for (int k = 0; k < fused_loads<DX>(); ++k) r[k] = m.src[k] >= 0 ? plane[m.src[k]] : 0.f;
+}
+
+template <int DX>
+__device__ __forceinline__ void fused_stage(float* __restrict__ slot, const FusedStage<DX>& m,
+                                            const float (&r)[fused_loads<DX>()]) {
+#pragma unroll
+  for (int k = 0; k < fused_loads<DX>(); ++k)
+    if (m.src[k] >= 0) slot[m.dst[k]] = r[k];
+}
+
+// Q = sum_m By_m (sum_l Bx_l phi[row + m][col + l]) from a staged plane: the
+// operations of the forward kernel's contraction (fwd_contract), in its order.
+template <int DX>
+__device__ __forceinline__ F3 fused_contract(const float* __restrict__ slot, int base, const float (&bx)[4],
+                                             const float (&by)[4]) {
+  constexpr int P = adj_cx_max(DX) * 3;  // floats per staged row
+  float q[3];
+  {
+    const float* p = slot + base;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      q[c] = by[0] * fmaf(bx[3], p[9 + c], fmaf(bx[2], p[6 + c], fmaf(bx[1], p[3 + c], bx[0] * p[c])));
+  }
+#pragma unroll 1
+  for (int m = 1; m < 4; ++m) {
+    const float* p = slot + base + m * P;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float r = fmaf(bx[3], p[9 + c], fmaf(bx[2], p[6 + c], fmaf(bx[1], p[3 + c], bx[0] * p[c])));
+      q[c] = fmaf(by[m], r, q[c]);
+    }
+  }
+  return F3{q[0], q[1], q[2]};
+}
+
+template <int DX, bool StageAll>
 __device__ __forceinline__ void fused_brick(const float* __restrict__ grid, const float* __restrict__ moving,
                                             const float* __restrict__ fixed, float* __restrict__ part,
                                             float* __restrict__ lpart, const AdjGeom& a,
-                                            const float* __restrict__ lut, int brick, FusedSmem<DX>& sm,
-                                            int tid) {
+                                            const float* __restrict__ lut, int brick, FusedSmem<DX>& sm, int tid) {
+  constexpr int R = 1;
+  constexpr int CXM = adj_cx_max(DX);
   const VolGeom& g = a.g;
   const int dx = DX > 0 ? DX : g.dx;
   const AdjBrick b = adj_brick_geom(a, brick);
-  float* pbase = part + (size_t)brick * a.z.cm * a.y.cm * a.x.cm * 3;
-  if constexpr (fused_voxel_layout(DX)) {
-    if (tid < 4 * DX) sm.wx[tid] = lut_row(lut, DX, 0)[tid];  // ordered by adj_tables' barrier
+  float* pbase = part + (size_t)brick * adj_brick_stride(a);
+  const int lane = tid & (kWave - 1), wave = uniform(tid / kWave);
+
+  // this lane's voxels: column x, rows y[r]; forward weights and window bases
+  const int x = b.x0 + lane;
+  const int xc = imin(x, b.xe - 1);
+  const int tx = xc / dx;
+  float bx[4];
+  {
+    const float* w = lut_row(lut, dx, xc - tx * dx);
+#pragma unroll
+    for (int l = 0; l < 4; ++l) bx[l] = w[l];
   }
-  adj_tables(a, b, lut, sm.e, tid);
+  int yv[R], base[R];
+  bool act[R];
+  float by[R][4];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    yv[r] = b.y0 + wave * R + r;
+    act[r] = x < b.xe && yv[r] < b.ye;
+    const int yc = imin(yv[r], b.ye - 1);
+    const int ty = yc / g.dy;
+    const float* w = lut_row(lut, g.dy, yc - ty * g.dy);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) by[r][m] = w[m];
+    base[r] = ((ty - b.cy0) * CXM + (tx - b.cx0)) * 3;
+  }
+  const FusedStage<DX> map = fused_stage_map<DX>(g, b, tid);
 
-  const int txl = tid % kAdjTilesX;
-  const int yl = tid / kAdjTilesX;
-  const int y = b.y0 + yl;
-  const int tx = b.cx0 + txl;
-  const bool row_in = y < b.ye;
-  const bool act = txl < b.ntx && row_in;
-  const int x0 = tx * dx;
-  const int nval = act ? min(dx, g.nx - x0) : 0;
-  const float* lutx = lut_row(lut, dx, 0);
-
-  // Control columns this thread contracts over y: its own (cx0 + txl) and, for
-  // txl < 3, cx0 + 16 + txl; both only when inside the brick's window (< Cx),
-  // which keeps every index below gx.  Rows outside the brick contract nothing.
-  const bool need_m = row_in && txl < b.Cx;
-  const bool need_w = row_in && txl < 3 && kAdjTilesX + txl < b.Cx;
-  const int yc = row_in ? y : b.y0;
-  const int ty = yc / g.dy;  // ty + 3 <= gy - 1
-  const float* wy = lut_row(lut, g.dy, yc - ty * g.dy);
-  const float by0 = wy[0], by1 = wy[1], by2 = wy[2], by3 = wy[3];
-  const size_t gplane = (size_t)g.gy * g.gx * 3, grow = (size_t)g.gx * 3;
-  const float* colm = grid + ((size_t)ty * g.gx + (need_m ? tx : 0)) * 3;
-  const float* colw = grid + ((size_t)ty * g.gx + (need_w ? tx + kAdjTilesX : 0)) * 3;
-  auto ycontract = [&](const float* col, int cz, bool need) {
-    F3 r{0.f, 0.f, 0.f};
-    if (need) {
-      const float* p = col + (size_t)cz * gplane;
-      const F3 q0 = ldf3(p), q1 = ldf3(p + grow), q2 = ldf3(p + 2 * grow), q3 = ldf3(p + 3 * grow);
-      r.x = fmaf(by3, q3.x, fmaf(by2, q2.x, fmaf(by1, q1.x, by0 * q0.x)));
-      r.y = fmaf(by3, q3.y, fmaf(by2, q2.y, fmaf(by1, q1.y, by0 * q0.y)));
-      r.z = fmaf(by3, q3.z, fmaf(by2, q2.z, fmaf(by1, q1.z, by0 * q0.z)));
+  // Q of the 4 control planes of the first z-tile, one plane staged at a time
+  int tz = b.cz0;  // z-bricks are whole tiles: b.z0 = tz * dz
+  F3 Q[R][4];
+  float st[fused_loads<DX>()];
+#pragma unroll 1
+  for (int j = 0; j < 4; ++j) {
+    __syncthreads();  // the slot's previous plane has been contracted (or a previous brick is done)
+    fused_fetch<DX>(grid, g, map, tz + j, st);
+    fused_stage<DX>(sm.ring[(tz + j) & 1], map, st);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const F3 q = fused_contract<DX>(sm.ring[(tz + j) & 1], base[r], bx, by[r]);
+#pragma unroll
+      for (int n = 0; n < 3; ++n) Q[r][n] = Q[r][n + 1];
+      Q[r][3] = q;
     }
-    return r;
+  }
+  // the next tile's new plane tz + 4 (when another tile follows inside the
+  // brick, it is at most ceil(nz/dz) + 2 = gz - 1)
+  bool more = (tz + 1) * g.dz < b.ze;
+  if (more) fused_fetch<DX>(grid, g, map, tz + 4, st);
+
+  F3 acc[R][4];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int n = 0; n < 4; ++n) acc[r][n] = F3{0.f, 0.f, 0.f};
+  float l2 = 0.f;
+  auto finish = [&](int czl, bool last) {
+    F3 f[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) f[r] = acc[r][0];
+    adj_emit_x<DX, R>(b, sm.adj, lut, dx, tid, czl, f);
+    __syncthreads();
+    adj_emit_y<DX, kFusedWaves, StageAll>(a, b, pbase, sm.adj, lut, tid, czl, last);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+      for (int n = 0; n < 3; ++n) acc[r][n] = acc[r][n + 1];
+      acc[r][3] = F3{0.f, 0.f, 0.f};
+    }
   };
 
-  int tz = b.cz0;
-  int oz = b.z0 - tz * g.dz;
-  F3 R[4], Rw[4];
-#pragma unroll
-  for (int n = 0; n < 4; ++n) {
-    R[n] = ycontract(colm, tz + n, need_m);
-    Rw[n] = ycontract(colw, tz + n, need_w);
-  }
-  F3 acc[4], accw[4];
-#pragma unroll
-  for (int n = 0; n < 4; ++n) acc[n] = accw[n] = F3{0.f, 0.f, 0.f};
-  float l2 = 0.f;
   const size_t izs = (size_t)g.ny * g.nx;
-  const float* fix = fixed + (size_t)b.z0 * izs + (size_t)(act ? y : 0) * g.nx + (act ? x0 : 0);
-
+  int oz = 0;
   for (int z = b.z0; z < b.ze; ++z) {
     const float* wz = lut_row(lut, g.dz, oz);
-    F3 M[4];
-    const F3 pm = zcombine(wz, R);  // P of column tx (every lane takes part)
-    const F3 pw = zcombine(wz, Rw); // P of column tx + 16 (lanes txl < 3)
-    if constexpr (fused_voxel_layout(DX)) {
-      const int lane = tid & (kWave - 1), wave = tid / kWave;
-      float* pl = sm.P + wave * (kAdjRowsPerWave * kFusedCols * 3);
-      float* tb = sm.T + wave * adj_wave_buf(DX);
-      const int ywave = b.y0 + wave * kAdjRowsPerWave;
-      wave_lds_sync();  // the previous plane's readers of pl and tb are done
-      {
-        const int r = lane / kAdjTilesX;
-        stf3(pl + (r * kFusedCols + txl) * 3, pm);
-        if (txl < 3) stf3(pl + (r * kFusedCols + kAdjTilesX + txl) * 3, pw);
-      }
-      wave_lds_sync();
-#if BSI_FUSED_FULL_UNROLL
+    const float w0 = wz[0], w1 = wz[1], w2 = wz[2], w3 = wz[3];
+    float fx[R];
 #pragma unroll
-#else
-#pragma unroll 2
-#endif
-      for (int k = 0; k < DX; ++k) {
-        const int v = k * kWave + lane;
-        const int r = v / (kAdjTilesX * DX);
-        const int xl = v - r * (kAdjTilesX * DX);
-        const int tl = xl / DX, o = xl - tl * DX;
-        const int xv = b.x0 + xl, yv = ywave + r;
-        F3 d{0.f, 0.f, 0.f};
-        if (xv < b.xe && yv < b.ye) {
-          const float* bx = sm.wx + 4 * o;
-          const float* pp = pl + (r * kFusedCols + tl) * 3;  // columns tl .. tl + 3 (<= 18)
-          F3 t;
-          t.x = fmaf(bx[3], pp[9], fmaf(bx[2], pp[6], fmaf(bx[1], pp[3], bx[0] * pp[0])));
-          t.y = fmaf(bx[3], pp[10], fmaf(bx[2], pp[7], fmaf(bx[1], pp[4], bx[0] * pp[1])));
-          t.z = fmaf(bx[3], pp[11], fmaf(bx[2], pp[8], fmaf(bx[1], pp[5], bx[0] * pp[2])));
-          const Sample smp = trilinear(moving, g.nx, g.ny, g.nz, (float)xv + t.x, (float)yv + t.y, (float)z + t.z);
-          const float res = smp.w - fixed[((size_t)z * g.ny + yv) * g.nx + xv];
-          l2 = fmaf(res, res, l2);
-          const float two_r = 2.f * res;
-          d = F3{two_r * smp.gx, two_r * smp.gy, two_r * smp.gz};
-        }
-        stf3(tb + v * 3, d);
-      }
-      wave_lds_sync();
-      adj_plane_moments<DX>(tb, lane, nval, lutx, M);
-    } else {
-      // P of the four columns tx..tx+3 of this plane (every lane takes part)
-      F3 P[4];
-      P[0] = pm;
-      P[1] = column_right<1>(txl, pm, pw);
-      P[2] = column_right<2>(txl, pm, pw);
-      P[3] = column_right<3>(txl, pm, pw);
+    for (int r = 0; r < R; ++r) fx[r] = act[r] ? fixed[(size_t)z * izs + (size_t)yv[r] * g.nx + x] : 0.f;
 #pragma unroll
-      for (int l = 0; l < 4; ++l) M[l] = F3{0.f, 0.f, 0.f};
-      auto voxel = [&](int o) {
-        const float* bx = lutx + 4 * o;
-        F3 t;
-        t.x = fmaf(bx[3], P[3].x, fmaf(bx[2], P[2].x, fmaf(bx[1], P[1].x, bx[0] * P[0].x)));
-        t.y = fmaf(bx[3], P[3].y, fmaf(bx[2], P[2].y, fmaf(bx[1], P[1].y, bx[0] * P[0].y)));
-        t.z = fmaf(bx[3], P[3].z, fmaf(bx[2], P[2].z, fmaf(bx[1], P[1].z, bx[0] * P[0].z)));
-        const Sample smp = trilinear(moving, g.nx, g.ny, g.nz, (float)(x0 + o) + t.x, (float)y + t.y,
-                                     (float)z + t.z);
-        const float res = smp.w - fix[o];
+    for (int r = 0; r < R; ++r) {
+      // T as the forward kernel forms it
+      const F3 t{fmaf(w3, Q[r][3].x, fmaf(w2, Q[r][2].x, fmaf(w1, Q[r][1].x, w0 * Q[r][0].x))),
+                 fmaf(w3, Q[r][3].y, fmaf(w2, Q[r][2].y, fmaf(w1, Q[r][1].y, w0 * Q[r][0].y))),
+                 fmaf(w3, Q[r][3].z, fmaf(w2, Q[r][2].z, fmaf(w1, Q[r][1].z, w0 * Q[r][0].z)))};
+      F3 d{0.f, 0.f, 0.f};
+      if (act[r]) {
+        // the SSD kernel's sample and gradient
+        const Sample s = trilinear(moving, g.nx, g.ny, g.nz, (float)x + t.x, (float)yv[r] + t.y, (float)z + t.z);
+        const float res = s.w - fx[r];
         l2 = fmaf(res, res, l2);
         const float two_r = 2.f * res;
-        const F3 d{two_r * smp.gx, two_r * smp.gy, two_r * smp.gz};
+        d = F3{two_r * s.gx, two_r * s.gy, two_r * s.gz};
+      }
+      // the adjoint's z-accumulation
+      const float ws[4] = {w0, w1, w2, w3};
 #pragma unroll
-        for (int l = 0; l < 4; ++l) {
-          M[l].x = fmaf(bx[l], d.x, M[l].x);
-          M[l].y = fmaf(bx[l], d.y, M[l].y);
-          M[l].z = fmaf(bx[l], d.z, M[l].z);
-        }
-      };
-#pragma unroll 1
-      for (int o = 0; o < nval; ++o) voxel(o);
-    }
-    fix += izs;
-
-    F3 cm, cw;
-    adj_xcombine(txl, M, cm, cw);
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
-      const float w = wz[n];
-      acc[n].x = fmaf(w, cm.x, acc[n].x);
-      acc[n].y = fmaf(w, cm.y, acc[n].y);
-      acc[n].z = fmaf(w, cm.z, acc[n].z);
-      accw[n].x = fmaf(w, cw.x, accw[n].x);
-      accw[n].y = fmaf(w, cw.y, accw[n].y);
-      accw[n].z = fmaf(w, cw.z, accw[n].z);
+      for (int n = 0; n < 4; ++n) {
+        acc[r][n].x = fmaf(ws[n], d.x, acc[r][n].x);
+        acc[r][n].y = fmaf(ws[n], d.y, acc[r][n].y);
+        acc[r][n].z = fmaf(ws[n], d.z, acc[r][n].z);
+      }
     }
     if (++oz == g.dz && z + 1 < b.ze) {
-      adj_emit(a, b, pbase, sm.e, tid, tz - b.cz0, tz - b.cz0, false, acc[0], accw[0]);
+      // plane tz + 4 goes to the slot of plane tz + 2, contracted before the
+      // previous tile's barrier; the emission's barrier orders the store
+      // before the contraction below
+      fused_stage<DX>(sm.ring[(tz + 4) & 1], map, st);
+      F3 f[R];
 #pragma unroll
-      for (int n = 0; n < 3; ++n) {
-        acc[n] = acc[n + 1];
-        accw[n] = accw[n + 1];
-        R[n] = R[n + 1];
-        Rw[n] = Rw[n + 1];
+      for (int r = 0; r < R; ++r) f[r] = acc[r][0];
+      adj_emit_x<DX, R>(b, sm.adj, lut, dx, tid, tz - b.cz0, f);
+      __syncthreads();
+      adj_emit_y<DX, kFusedWaves, StageAll>(a, b, pbase, sm.adj, lut, tid, tz - b.cz0, false);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int n = 0; n < 3; ++n) {
+          acc[r][n] = acc[r][n + 1];
+          Q[r][n] = Q[r][n + 1];
+        }
+        acc[r][3] = F3{0.f, 0.f, 0.f};
+        Q[r][3] = fused_contract<DX>(sm.ring[(tz + 4) & 1], base[r], bx, by[r]);
       }
-      acc[3] = accw[3] = F3{0.f, 0.f, 0.f};
-      // the next tile tz + 1 lies inside the brick, so its last plane
-      // tz + 4 <= ceil(nz/dz) + 2 = gz - 1
-      R[3] = ycontract(colm, tz + 4, need_m);
-      Rw[3] = ycontract(colw, tz + 4, need_w);
-      oz = 0;
       ++tz;
+      oz = 0;
+      more = (tz + 1) * g.dz < b.ze;
+      if (more) fused_fetch<DX>(grid, g, map, tz + 4, st);
     }
   }
 #pragma unroll 1
-  for (int n = 0; n < 4; ++n) {
-    adj_emit(a, b, pbase, sm.e, tid, tz - b.cz0 + n, tz - b.cz0 + n, n == 3, acc[0], accw[0]);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      acc[j] = acc[j + 1];
-      accw[j] = accw[j + 1];
-    }
-  }
+  for (int n = 0; n < 4; ++n) finish(tz - b.cz0 + n, n == 3);
 
   // loss partial of the brick: fixed-order tree over the workgroup
   sm.red[tid] = l2;
   __syncthreads();
-  for (int h = kAdjThreads / 2; h > 0; h >>= 1) {
+  for (int h = kFusedThreads / 2; h > 0; h >>= 1) {
     if (tid < h) sm.red[tid] += sm.red[tid + h];
     __syncthreads();
   }
@@ -269,17 +276,20 @@ __device__ __forceinline__ void fused_brick(const float* __restrict__ grid, cons
 }
 
 template <int DX>
-__global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(4))) void fused_pass1_kernel(const float* __restrict__ grid,
-                                                                   const float* __restrict__ moving,
-                                                                   const float* __restrict__ fixed,
-                                                                   float* __restrict__ part,
-                                                                   float* __restrict__ lpart, AdjGeom a,
-                                                                   const float* __restrict__ lut) {
+__global__ __launch_bounds__(kFusedThreads) void fused_pass1_kernel(const float* __restrict__ grid,
+                                                                  const float* __restrict__ moving,
+                                                                  const float* __restrict__ fixed,
+                                                                  float* __restrict__ part,
+                                                                  float* __restrict__ lpart, AdjGeom a,
+                                                                  const float* __restrict__ lut) {
   __shared__ FusedSmem<DX> sm;
   const int nbricks = a.x.nb * a.y.nb * a.z.nb;
   const int brick = xcd_remap(blockIdx.x, gridDim.x);
   if (brick >= nbricks) return;  // uniform over the workgroup
-  fused_brick<DX>(grid, moving, fixed, part, lpart, a, lut, brick, sm, threadIdx.x);
+  if (adj_stage_all(a))
+    fused_brick<DX, true>(grid, moving, fixed, part, lpart, a, lut, brick, sm, threadIdx.x);
+  else
+    fused_brick<DX, false>(grid, moving, fixed, part, lpart, a, lut, brick, sm, threadIdx.x);
 }
 
 }  // namespace
@@ -295,12 +305,12 @@ hipError_t launch_ssd_fused(const float* grid, const float* moving, const float*
   float* lpart = reinterpret_cast<float*>(static_cast<char*>(workspace) +
                                           (adj_workspace_bytes(a) + 255) / 256 * 256);
   const long nbricks = (long)a.x.nb * a.y.nb * a.z.nb;
-  const dim3 gridd((unsigned)nbricks), block(kAdjThreads);
-#define BSI_FUSED_CASE(D)                                                                           \
-  case D:                                                                                          \
-    hipLaunchKernelGGL(fused_pass1_kernel<D>, gridd, block, 0, s, grid, moving, fixed, part, lpart, a, \
-                       lut);                                                                       \
+  const dim3 gridd((unsigned)nbricks), block(kFusedThreads);
+#define BSI_FUSED_CASE(D)                                                                               \
+  case D:                                                                                               \
+    hipLaunchKernelGGL(fused_pass1_kernel<D>, gridd, block, 0, s, grid, moving, fixed, part, lpart, a, lut); \
     break;
+  static_assert(kAdjMaxDX == 12, "one case per specialised spacing");
   switch (a.g.dx) {
     BSI_FUSED_CASE(1)
     BSI_FUSED_CASE(2)
@@ -310,6 +320,10 @@ hipError_t launch_ssd_fused(const float* grid, const float* moving, const float*
     BSI_FUSED_CASE(6)
     BSI_FUSED_CASE(7)
     BSI_FUSED_CASE(8)
+    BSI_FUSED_CASE(9)
+    BSI_FUSED_CASE(10)
+    BSI_FUSED_CASE(11)
+    BSI_FUSED_CASE(12)
     default: BSI_FUSED_CASE(0)
   }
 #undef BSI_FUSED_CASE

@@ -31,34 +31,29 @@ struct Check {
     if (!(c)) return ck.fail(std::string(what) + " [" #c "]");                   \
   } while (0)
 
-// Loads and LDS indices of the z-first pass 1 (adjz_brick) for one brick.
-bool check_adjz_brick(const AdjGeom& a, const AdjBrick& b, Check& ck) {
+// Loads and LDS indices of pass 1 (adj_brick) for one brick.
+bool check_adj_brick(const AdjGeom& a, const AdjBrick& b, Check& ck) {
   const size_t plane = (size_t)a.g.nx * a.g.ny * 3;
   REQUIRE(b.z0 == b.cz0 * a.g.dz, "z-bricks start on tile boundaries (the march starts at offset 0)");
-  REQUIRE(b.xe - b.x0 <= kAdjZBX && b.ye - b.y0 <= kAdjZBY, "brick within one lane per voxel and row");
+  REQUIRE(b.xe - b.x0 <= kAdjBX && b.ye - b.y0 <= kAdjBY, "brick within one lane per voxel and row");
   const int dxc = a.g.dx <= kAdjMaxDX ? a.g.dx : 0;
-  REQUIRE(b.Cx <= adjz_cx_max(dxc), "x window within the H buffer's row");
-  REQUIRE(b.Cy <= kAdjZCyMax, "y window within the y tables");
-  for (int w = 0; w < kAdjZWaves; ++w)
+  REQUIRE(b.Cx <= adj_cx_max(dxc), "x window within the H buffer's row");
+  REQUIRE(b.Cy - 3 <= kAdjTiles, "y-tiles within one row of tile lanes");
+  if (adj_tile_lanes(dxc)) REQUIRE(b.ntx <= kAdjTiles, "x-tiles within one row of tile lanes");
+  if (adj_stage_all(a)) REQUIRE((size_t)adj_brick_cz(a, b) * a.y.cm * a.x.cm * 3 <= (size_t)kAdjStageFloats,
+                                "staged partials within the LDS stage");
+  for (int w = 0; w < kAdjWaves; ++w)
     for (int lane = 0; lane < kWave; ++lane) {
-      uint32_t off[kAdjZRows];
-      adjz_offsets<kAdjZRows>(b, a.g.nx, w, lane, off);
-      for (int r = 0; r < kAdjZRows; ++r) {
+      uint32_t off[kAdjRows];
+      adj_offsets<kAdjRows>(b, a.g.nx, w, lane, off);
+      for (int r = 0; r < kAdjRows; ++r) {
         REQUIRE((size_t)off[r] + 3 <= plane, "pass-1 load outside its voxel plane");
         const int x = (int)(off[r] / 3 % a.g.nx), y = (int)(off[r] / 3 / a.g.nx);
         REQUIRE(x >= b.x0 && x < b.xe && y >= b.y0 && y < b.ye, "pass-1 load outside its brick");
       }
     }
-  return true;
-}
-
-// Brick geometry of the fused step's pass 1 (x-tile lanes, fused_brick).
-bool check_fused_brick(const AdjGeom& a, const AdjBrick& b, Check& ck) {
-  REQUIRE(b.ntx >= 1 && b.ntx <= kAdjTilesX, "x-tiles per brick (one lane each)");
-  REQUIRE(b.ye - b.y0 <= kAdjMaxY, "rows per brick (one lane row each)");
-  REQUIRE(b.x0 == b.cx0 * a.g.dx, "x-bricks start on tile boundaries");
-  REQUIRE(b.Cx <= kAdjMaxCx, "x window (LDS slot)");
-  REQUIRE(b.Cy <= kAdjMaxCy, "y window (LDS tables)");
+  // the fused step stages each control plane's window (Cy rows x Cx points)
+  REQUIRE(b.Cy <= kAdjBY + 3, "fused staging rows");
   return true;
 }
 
@@ -133,10 +128,7 @@ bool check_adjoint(const AdjGeom& a, BrickCheck brick_check, Check& ck) {
   return true;
 }
 
-bool check_adjoints(const VolGeom& g, Check& ck) {
-  return check_adjoint(make_adj_geom(g), check_adjz_brick, ck) &&
-         check_adjoint(make_fused_geom(g), check_fused_brick, ck);
-}
+bool check_adjoints(const VolGeom& g, Check& ck) { return check_adjoint(make_adj_geom(g), check_adj_brick, ck); }
 
 // The marching forward (fwd_block) with workgroup shape T and C components.
 template <int C, class T>
