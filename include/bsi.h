@@ -136,6 +136,24 @@ int32_t bsi_adjoint_reduce(const void* workspace, size_t workspace_bytes,
                            const int32_t dims[3], const int32_t spacing[3],
                            float* grid_grad, hipStream_t stream);
 
+/* The adjoint of bsi_adjoint without its workspace arguments, and without
+   any allocation.  For callers that cannot allocate device memory: code
+   under HIP graph capture, tight serving loops, harnesses that forbid
+   hipMalloc.  Same kernels and same bits as bsi_adjoint.
+   The partials live in a static device array of BSI_ADJOINT_NOALLOC_MAX_BYTES
+   that each GPU the library runs on holds until the process ends; all calls on
+   one GPU share it, so calls that may overlap on one GPU (other streams or
+   host threads) race, and the caller must order them.  The first call on a
+   device (of this or any other entry point) uploads the basis table with a
+   blocking copy: make it outside graph capture.
+   Arguments, layouts and ownership as in bsi_adjoint; grid_grad OVERWRITTEN.
+   Errors: INVALID_ARG, UNSUPPORTED (also when this geometry's partials,
+   bsi_adjoint_workspace_size(), exceed BSI_ADJOINT_NOALLOC_MAX_BYTES),
+   NO_DEVICE, HIP. */
+#define BSI_ADJOINT_NOALLOC_MAX_BYTES ((size_t)64 << 20) /* 64 MiB per device */
+int32_t bsi_adjoint_noalloc(const float* dfield, const int32_t dims[3], const int32_t spacing[3],
+                            float* grid_grad, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------
  * Control grids with real spacing and an origin offset (the paper's method
  * needs the grid aligned to the voxels with integer spacing, Sec. 3.4; Sec. 8

@@ -27,7 +27,7 @@ BSI_MAX_SPACING = 64
 EXPORTS = (
     "bsi_version", "bsi_last_error", "bsi_grid_dims", "bsi_forward", "bsi_forward_lerp", "bsi_forward_scalar",
     "bsi_adjoint_workspace_size",
-    "bsi_adjoint", "bsi_adjoint_partials", "bsi_adjoint_reduce", "bsi_general_grid_dims",
+    "bsi_adjoint", "bsi_adjoint_partials", "bsi_adjoint_reduce", "bsi_adjoint_noalloc", "bsi_general_grid_dims",
     "bsi_forward_general", "bsi_adjoint_general_workspace_size", "bsi_adjoint_general", "bsi_warp", "bsi_ssd_workspace_size", "bsi_ssd_grad", "bsi_ssd_fused_workspace_size", "bsi_ssd_fused",
     "bsi_descent_step",
     "bsi_batch_create", "bsi_batch_bind", "bsi_batch_tune", "bsi_batch_config", "bsi_batch_run",
@@ -67,6 +67,7 @@ def lib():
         "bsi_adjoint_workspace_size": ([p3, p3, ctypes.POINTER(sz)], i32),
         "bsi_adjoint": ([_VP, p3, p3, _VP, _VP, sz, _VP], i32),
         "bsi_adjoint_partials": ([_VP, p3, p3, _VP, sz, _VP], i32),
+        "bsi_adjoint_noalloc": ([_VP, p3, p3, _VP, _VP], i32),
         "bsi_general_grid_dims": ([p3, pf3, pf3, p3], i32),
         "bsi_forward_general": ([_VP, p3, pf3, pf3, _VP, _VP], i32),
         "bsi_adjoint_general_workspace_size": ([p3, pf3, pf3, ctypes.POINTER(sz)], i32),
@@ -232,6 +233,18 @@ def bsi_adjoint_reduce(workspace, dims, spacing, grid_grad, stream=None):
     w, nbytes = _workspace(workspace)
     _check(lib().bsi_adjoint_reduce(w, nbytes, _triple(dims, "dims"), _triple(spacing, "spacing"), g,
                                     _stream(stream)))
+
+
+def bsi_adjoint_noalloc(dfield, dims, spacing, grid_grad, stream=None):
+    """bsi_adjoint without a workspace and without allocating: the partials go to
+    the library's fixed per-device scratch array (BSI_ADJOINT_NOALLOC_MAX_BYTES);
+    calls that may overlap on one GPU race on it."""
+    d = _ptr(dfield, "dfield", field_shape(dims))
+    g = _ptr(grid_grad, "grid_grad", grid_shape(dims, spacing))
+    _check(lib().bsi_adjoint_noalloc(d, _triple(dims, "dims"), _triple(spacing, "spacing"), g, _stream(stream)))
+
+
+BSI_ADJOINT_NOALLOC_MAX_BYTES = 64 << 20
 
 
 def _workspace(workspace):

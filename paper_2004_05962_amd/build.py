@@ -25,7 +25,7 @@ CHECK_LIB = os.path.join(HERE, "libbsi_check.so")
 CHECK_SRC = "index_check.cpp"
 OBJDIR = os.path.join(ROOT, "_build", "obj")
 
-SOURCES = ["lut.hip", "forward.hip", "lerp.hip", "adjoint.hip", "warp.hip", "fused.hip", "general.hip", "batch.hip", "abi.cpp"]
+SOURCES = ["lut.hip", "forward.hip", "lerp.hip", "adjoint.hip", "warp.hip", "fused.hip", "general.hip", "batch.hip", "noalloc.hip", "abi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

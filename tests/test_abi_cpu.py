@@ -193,3 +193,22 @@ def test_general_window_start_is_the_exact_floor():
     for n, s, o in cases:
         got = bsi.bsi_general_grid_dims((n, 1, 1), (s, 1.0, 1.0), (o, 0.0, 0.0))[0]
         assert got == general.grid_dims((n, 1, 1), (s, 1.0, 1.0), (o, 0.0, 0.0))[0], (n, s, o)
+
+
+def test_noalloc_rejects_geometry_beyond_its_scratch_before_device():
+    """bsi_adjoint_noalloc checks the partials' size against its fixed scratch
+    (BSI_ADJOINT_NOALLOC_MAX_BYTES) on the host, before any device call."""
+    text = open(HEADER).read()
+    m = re.search(r"#define BSI_ADJOINT_NOALLOC_MAX_BYTES \(\(size_t\)(\d+) << (\d+)\)", text)
+    assert m, "the header states the scratch size"
+    cap = int(m.group(1)) << int(m.group(2))
+    assert cap == _lib.BSI_ADJOINT_NOALLOC_MAX_BYTES
+    P = ctypes.c_void_p(16)  # never dereferenced: rejected before any device use
+    big = (512, 512, 256), (2, 2, 2)
+    assert bsi.bsi_adjoint_workspace_size(*big) > cap
+    rc = _call("bsi_adjoint_noalloc", P, _t(big[0]), _t(big[1]), P, NULL)
+    assert rc == _lib.BSI_ERR_UNSUPPORTED
+    assert "scratch" in bsi.bsi_last_error()
+    # the benchmark geometry fits
+    assert bsi.bsi_adjoint_workspace_size((512, 512, 256), (5, 5, 5)) <= cap
+    assert _call("bsi_adjoint_noalloc", NULL, _t((8, 8, 8)), _t((2, 2, 2)), P, NULL) == _lib.BSI_ERR_INVALID_ARG
