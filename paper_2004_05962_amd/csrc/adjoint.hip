@@ -18,18 +18,9 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(BSI
     adj_brick<DX, true, false>(dfield, part, a, lut, brick, sm, threadIdx.x);
 }
 
-constexpr int kGatherThreads = 256;
-
 __global__ __launch_bounds__(kGatherThreads) void adj_pass2_kernel(const float* __restrict__ part,
                                                                     float* __restrict__ grad, AdjGeom a) {
-  const int64_t n = (int64_t)a.g.gx * a.g.gy * a.g.gz;
-  const int64_t i = (int64_t)blockIdx.x * kGatherThreads + threadIdx.x;
-  if (i >= n) return;
-  const int cx = (int)(i % a.g.gx);
-  const int64_t r = i / a.g.gx;
-  const int cy = (int)(r % a.g.gy);
-  const int cz = (int)(r / a.g.gy);
-  stf3(grad + i * 3, adj_gather_point(part, a, cx, cy, cz));
+  adj_gather_block(part, grad, a, blockIdx.x, threadIdx.x);
 }
 
 namespace {
@@ -88,9 +79,9 @@ hipError_t launch_adjoint_partials(const float* dfield, const AdjGeom& a, const 
 }
 
 hipError_t launch_adjoint_reduce(const float* part, float* grad, const AdjGeom& a, hipStream_t s) {
-  const long npts = (long)a.g.gx * a.g.gy * a.g.gz;
-  hipLaunchKernelGGL(adj_pass2_kernel, dim3((unsigned)((npts + kGatherThreads - 1) / kGatherThreads)),
-                     dim3(kGatherThreads), 0, s, part, grad, a);
+  const int64_t nblk = adj_gather_blocks(a.g);
+  if (nblk >= ((int64_t)1 << 31)) return hipErrorInvalidConfiguration;  // a field far beyond device memory
+  hipLaunchKernelGGL(adj_pass2_kernel, dim3((unsigned)nblk), dim3(kGatherThreads), 0, s, part, grad, a);
   return hipGetLastError();
 }
 

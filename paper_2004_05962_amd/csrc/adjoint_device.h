@@ -25,6 +25,8 @@
 // anywhere: the bits depend on the inputs only.
 #pragma once
 
+#include <type_traits>
+
 #include "bsi_device.h"
 
 namespace bsi {
@@ -43,16 +45,12 @@ namespace bsi {
 #ifndef BSI_ADJ_WPE
 #define BSI_ADJ_WPE 6
 #endif
-#ifndef BSI_ADJ_AHEAD
-#define BSI_ADJ_AHEAD 2
-#endif
 constexpr int kAdjRows = BSI_ADJ_ROWS;             // rows per lane (R)
 constexpr int kAdjWaves = BSI_ADJ_WAVES;           // waves per workgroup
 constexpr int kAdjThreads = kAdjWaves * kWave;
 constexpr int kAdjBX = kWave;                      // brick width (voxels): one lane per voxel
 constexpr int kAdjBY = kAdjWaves * kAdjRows;       // brick height (rows)
 constexpr int kAdjTargetZ = BSI_ADJ_TARGET_Z;      // brick depth bound (voxels, at least one tile)
-constexpr int kAdjAhead = BSI_ADJ_AHEAD;           // voxel planes of loads in flight per wave
 constexpr int kAdjMaxDX = 12;                      // largest x spacing with its own kernel
 constexpr int kAdjTiles = 16;                      // tile lanes per row of lanes (DPP rows)
 // A brick of at most 16 rows meets at most 16 y-tiles (16 at spacing 1, at
@@ -83,9 +81,22 @@ __host__ __device__ constexpr bool adj_tile_lanes(int dx) { return dx == 0 || dx
 #endif
 constexpr int kAdjStageFloats = BSI_ADJ_STAGE_FLOATS;  // 24 KB
 
+// Rows of H the y-contraction loads at once (one LDS round trip per group).
+#ifndef BSI_ADJ_YGROUP
+#define BSI_ADJ_YGROUP 1
+#endif
+constexpr int kAdjYGroup = BSI_ADJ_YGROUP;
+
+// Rows of the finished-plane buffer F carry dx - 1 voxels of zeros on each
+// side at x spacings 4..12, so a tile that reaches past the brick is
+// contracted without a test per voxel: its voxels outside the brick read zero
+// (the voxels of a ragged brick's row past its end are written as zeros too).
+__host__ __device__ constexpr int adj_fpad(int dx) { return dx >= 4 && dx <= kAdjMaxDX ? dx - 1 : 0; }
+__host__ __device__ constexpr int adj_frow(int dx) { return kWave + 2 * adj_fpad(dx); }  // row stride (voxels)
+
 template <int DX>
 struct AdjSmem {
-  float F[kAdjBY * kWave * 3];               // finished plane, row by row (each wave writes its own rows)
+  float F[kAdjBY * adj_frow(DX) * 3];        // finished plane, row by row (each wave writes its own rows)
   float H[2][kAdjBY * adj_cx_max(DX) * 3];   // x-contracted rows, double-buffered
   float P[kAdjStageFloats];                  // the brick's partial planes awaiting their store
 };
@@ -137,6 +148,35 @@ __host__ __device__ inline size_t adj_part_offset(const AdjGeom& a, int czl, int
 // points) fits the LDS stage; otherwise each plane is stored as it is finished.
 __host__ __device__ inline bool adj_stage_all(const AdjGeom& a) {
   return (long)a.z.cm * a.y.cm * a.x.cm * 3 <= kAdjStageFloats;
+}
+
+// Voxel 0 of brick row `row` in F (voxels -fpad .. 63 + fpad are addressable).
+template <int DX>
+__device__ __forceinline__ float* adj_frow_ptr(AdjSmem<DX>& sm, int row) {
+  return sm.F + (row * adj_frow(DX) + adj_fpad(DX)) * 3;
+}
+
+// This wave's R rows of F get voxel `lane` of the finished plane (zero past
+// the brick's end).
+template <int DX, int R>
+__device__ __forceinline__ void adj_put_f(AdjSmem<DX>& sm, const AdjBrick& b, int wave, int lane, int r, F3 v) {
+  if (lane >= b.xe - b.x0) v = F3{0.f, 0.f, 0.f};
+  stf3(adj_frow_ptr<DX>(sm, wave * R + r) + lane * 3, v);
+}
+
+// Zero the pads of this wave's R rows of F (wave-local: the wave's next
+// wave_lds_sync orders it before the x-contraction reads them).
+template <int DX, int R>
+__device__ __forceinline__ void adj_zero_fpad(AdjSmem<DX>& sm, int wave, int lane) {
+  constexpr int P = adj_fpad(DX);
+  if constexpr (P > 0) {
+    for (int i = lane; i < R * 2 * P * 3; i += kWave) {
+      const int r = i / (2 * P * 3), j = i - r * (2 * P * 3);  // j: float within the row's two pads
+      const int v = j / 3, c = j - v * 3;                       // pad voxel, component
+      const int xl = v < P ? v - P : kWave + (v - P);
+      adj_frow_ptr<DX>(sm, wave * R + r)[xl * 3 + c] = 0.f;
+    }
+  }
 }
 
 // Value of lane (i - N) mod 16 of this lane's row of 16 lanes (DPP row_ror).
@@ -236,20 +276,31 @@ __device__ __forceinline__ F3 adj_xsum(const float* __restrict__ Fr, const AdjBr
 
 // First half of a finished plane's emission (collective over the workgroup,
 // wave-local work) for workgroups of W waves of R rows each (W R = kAdjBY):
-// this wave's rows of the plane (f[r], lane = voxel) go through its rows of
-// the LDS buffer F and are contracted over x into H[czl & 1].  The caller then
-// places one workgroup barrier and calls adj_emit_y.
+// this wave's rows of the plane (lane = voxel; get(r) gives row r) go through
+// its rows of the LDS buffer F and are contracted over x into H[czl & 1].  The caller then places one
+// workgroup barrier and calls adj_emit_y.
 template <int DX, int R>
+__device__ __forceinline__ void adj_emit_xf(const AdjBrick& b, AdjSmem<DX>& sm, const float* __restrict__ lut,
+                                            int dx, int tid, int czl);
+
+template <int DX, int R, class Get>
 __device__ __forceinline__ void adj_emit_x(const AdjBrick& b, AdjSmem<DX>& sm, const float* __restrict__ lut,
-                                           int dx, int tid, int czl, const F3 (&f)[R]) {
+                                           int dx, int tid, int czl, Get get) {
+  const int lane = tid & (kWave - 1), wave = tid / kWave;
+  wave_lds_sync();  // this wave's x-contraction of the previous plane is done with its rows of F
+#pragma unroll
+  for (int r = 0; r < R; ++r) adj_put_f<DX, R>(sm, b, wave, lane, r, get(r));
+  wave_lds_sync();
+  adj_emit_xf<DX, R>(b, sm, lut, dx, tid, czl);
+}
+
+// The x-contraction of this wave's rows, already in F.
+template <int DX, int R>
+__device__ __forceinline__ void adj_emit_xf(const AdjBrick& b, AdjSmem<DX>& sm, const float* __restrict__ lut,
+                                            int dx, int tid, int czl) {
   static_assert(kWave / kAdjTiles >= R, "a wave's rows fit its rows of 16 tile lanes");
   constexpr int CXM = adj_cx_max(DX);
   const int lane = tid & (kWave - 1), wave = tid / kWave;
-  float* Fw = sm.F + wave * R * kWave * 3;
-  wave_lds_sync();  // this wave's x-contraction of the previous plane is done with Fw
-#pragma unroll
-  for (int r = 0; r < R; ++r) stf3(Fw + (r * kWave + lane) * 3, f[r]);
-  wave_lds_sync();
   float* H = sm.H[czl & 1];  // czl counts the brick's finished planes
   const int nrow = b.ye - b.y0 - wave * R;  // this wave's rows inside the brick
   if constexpr (adj_tile_lanes(DX)) {
@@ -262,18 +313,24 @@ __device__ __forceinline__ void adj_emit_x(const AdjBrick& b, AdjSmem<DX>& sm, c
     for (int l = 0; l < 4; ++l) M[l] = F3{0.f, 0.f, 0.f};
     if (act) {
       const int xt = (b.cx0 + t) * dx - b.x0;  // the tile's first voxel, brick-relative (may be < 0)
-      const float* Fr = Fw + rr * kWave * 3;
-      const int nxb = b.xe - b.x0;
-      auto voxel = [&](int o) {
-        const int xl = xt + o;
-        if (xl >= 0 && xl < nxb) adj_moment_step(lut_row(lut, dx, o), ldf3(Fr + xl * 3), M);
-      };
-      // pairs of voxels in flight: few registers while the z-accumulators and
-      // the next planes' loads are live
+      const float* Fr = adj_frow_ptr<DX>(sm, wave * R + rr);
+      if constexpr (adj_fpad(DX) > 0) {
+        // voxels xt .. xt + dx - 1 lie in -(dx - 1) .. 63 + dx - 1: no tests
+#pragma unroll
+        for (int o = 0; o < DX; ++o) adj_moment_step(lut_row(lut, DX, o), ldf3(Fr + (xt + o) * 3), M);
+      } else {
+        const int nxb = b.xe - b.x0;
+        auto voxel = [&](int o) {
+          const int xl = xt + o;
+          if (xl >= 0 && xl < nxb) adj_moment_step(lut_row(lut, dx, o), ldf3(Fr + xl * 3), M);
+        };
+        // pairs of voxels in flight: few registers while the z-accumulators
+        // and the next planes' loads are live
 #pragma unroll 1
-      for (int o = 0; o < dx; o += 2) {
-        voxel(o);
-        if (o + 1 < dx) voxel(o + 1);
+        for (int o = 0; o < dx; o += 2) {
+          voxel(o);
+          if (o + 1 < dx) voxel(o + 1);
+        }
       }
     }
     F3 cm, cw;
@@ -287,7 +344,7 @@ __device__ __forceinline__ void adj_emit_x(const AdjBrick& b, AdjSmem<DX>& sm, c
     const int items = imin(nrow, R) * b.Cx;
     for (int it = lane; it < items; it += kWave) {
       const int r = it / b.Cx, cxl = it - r * b.Cx;
-      stf3(H + ((wave * R + r) * CXM + cxl) * 3, adj_xsum<DX>(Fw + r * kWave * 3, b, b.cx0 + cxl, lut));
+      stf3(H + ((wave * R + r) * CXM + cxl) * 3, adj_xsum<DX>(adj_frow_ptr<DX>(sm, wave * R + r), b, b.cx0 + cxl, lut));
     }
   }
 }
@@ -318,11 +375,23 @@ __device__ __forceinline__ void adj_emit_y(const AdjGeom& a, const AdjBrick& b, 
 #pragma unroll
     for (int m = 0; m < 4; ++m) N[m] = F3{0.f, 0.f, 0.f};
     const int y1 = (b.cy0 + ty) * g.dy;  // the tile's first row
-    const float* hp = H + ((y1 - b.y0) * CXM + cxl) * 3;
+    const float* hc = H + (act ? cxl : 0) * 3;
+    // rows in groups of kAdjYGroup, loaded together (a row outside the brick, or of
+    // an idle lane, reads a valid row and counts as zero); the trip counts are
+    // uniform, so the weights are scalar loads
 #pragma unroll 1
-    for (int oy = 0; oy < g.dy; ++oy) {  // uniform trip count: scalar weight loads
-      const int y = y1 + oy;
-      if (act && y >= b.y0 && y < b.ye) adj_moment_step(lut_row(lut, g.dy, oy), ldf3(hp + oy * CXM * 3), N);
+    for (int oy0 = 0; oy0 < g.dy; oy0 += kAdjYGroup) {
+      F3 v[kAdjYGroup];
+#pragma unroll
+      for (int j = 0; j < kAdjYGroup; ++j) {
+        const int y = y1 + oy0 + j;
+        const bool ok = act && oy0 + j < g.dy && y >= b.y0 && y < b.ye;
+        v[j] = ldf3(hc + (ok ? y - b.y0 : 0) * CXM * 3);
+        if (!ok) v[j] = F3{0.f, 0.f, 0.f};
+      }
+#pragma unroll
+      for (int j = 0; j < kAdjYGroup; ++j)
+        if (oy0 + j < g.dy) adj_moment_step(lut_row(lut, g.dy, oy0 + j), v[j], N);
     }
     F3 gm, gw;
     adj_combine(ty, N, gm, gw);  // every lane of the wave takes part
@@ -369,74 +438,96 @@ __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, floa
   const size_t zs = (size_t)g.ny * g.nx * 3;
   const float* plane0 = dfield + (size_t)b.z0 * zs;
 
-  F3 acc[R][4];
+  // acc[k][r]: the z-accumulation of control plane c for row r, in slot
+  // k = (c - cz0) & 3, so the accumulators never move: in tile t (phase
+  // ph = t & 3) slot k takes weight Bz_((k - ph) & 3), and slot ph holds the
+  // plane that finishes with the tile.  (The slot code below is written out
+  // in this function, not in lambdas: every access to acc must be visible
+  // with a constant index when it is promoted to registers.)
+  F3 acc[4][R];
 #pragma unroll
-  for (int r = 0; r < R; ++r)
+  for (int k = 0; k < 4; ++k)
 #pragma unroll
-    for (int n = 0; n < 4; ++n) acc[r][n] = F3{0.f, 0.f, 0.f};
-  int tz = b.cz0;  // z-bricks are whole tiles: b.z0 = tz * dz
-  int oz = 0;
-  auto emit0 = [&](int czl, bool last) {
-    F3 f[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) f[r] = acc[r][0];
-    adj_emit_x<DX, R>(b, sm, lut, dx, tid, czl, f);
-    __syncthreads();
-    adj_emit_y<DX, kAdjWaves, StageAll>(a, b, pbase, sm, lut, tid, czl, last);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-#pragma unroll
-      for (int n = 0; n < 3; ++n) acc[r][n] = acc[r][n + 1];
-      acc[r][3] = F3{0.f, 0.f, 0.f};
-    }
-  };
-  // One voxel plane: z-accumulation, then the loads of the plane kAdjAhead
-  // planes ahead into the same registers (when that plane exists), then the
-  // emission when a z-tile ends.
-  const float* ahead = plane0 + (size_t)kAdjAhead * zs;  // the plane kAdjAhead ahead of the next one
-  auto consume = [&](F3 (&d)[R], int z, bool load) {
-    const float* wz = lut_row(lut, g.dz, oz);
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
-      const float w = wz[n];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        acc[r][n].x = fmaf(w, d[r].x, acc[r][n].x);
-        acc[r][n].y = fmaf(w, d[r].y, acc[r][n].y);
-        acc[r][n].z = fmaf(w, d[r].z, acc[r][n].z);
-      }
-    }
-    if (load) adj_load<Stream>(ahead, off, d);
-    ahead += zs;
-    if (++oz == g.dz && z + 1 < b.ze) {
-      emit0(tz - b.cz0, false);
-      oz = 0;
-      ++tz;
-    }
-  };
-  // kAdjAhead register sets, each holding one plane's loads.  The loop is
-  // unrolled over them, and its main part runs only while every plane of the
-  // group and every plane kAdjAhead ahead exists, so its loads are
-  // unconditional: each set keeps fixed registers, and waiting for one set's
-  // loads leaves the other sets' loads in flight.  (The first sets are loaded
-  // unconditionally, from the brick's last plane when it is shallower, so the
-  // loop is entered with the same loads in flight on every path.)
-  F3 d[kAdjAhead][R];
-#pragma unroll
-  for (int j = 0; j < kAdjAhead; ++j) adj_load<Stream>(plane0 + (size_t)imin(j, b.ze - b.z0 - 1) * zs, off, d[j]);
+    for (int r = 0; r < R; ++r) acc[k][r] = F3{0.f, 0.f, 0.f};
+  adj_zero_fpad<DX, R>(sm, wave, lane);
+  int t = 0;   // tile index within the brick (z-bricks are whole tiles: b.z0 = cz0 dz)
+  int oz = 0;  // offset within the tile
+  const float* ahead = plane0 + 2 * zs;  // the plane two ahead of the next one
+
+// Control plane CZL, in slot PH (uniform), goes to this wave's rows of F (the
+// selects read every slot; each slot is cleared by its own select), then the
+// shared emission.
+#define BSI_ADJ_EMIT(CZL, PH, LAST)                                                        \
+  {                                                                                      \
+    const int ph_ = (PH);                                                                \
+    wave_lds_sync(); /* this wave's x-contraction of the previous plane is done with F */ \
+    _Pragma("unroll") for (int r = 0; r < R; ++r) {                                      \
+      F3 v;                                                                              \
+      v.x = ph_ == 0 ? acc[0][r].x : ph_ == 1 ? acc[1][r].x : ph_ == 2 ? acc[2][r].x : acc[3][r].x; \
+      v.y = ph_ == 0 ? acc[0][r].y : ph_ == 1 ? acc[1][r].y : ph_ == 2 ? acc[2][r].y : acc[3][r].y; \
+      v.z = ph_ == 0 ? acc[0][r].z : ph_ == 1 ? acc[1][r].z : ph_ == 2 ? acc[2][r].z : acc[3][r].z; \
+      adj_put_f<DX, R>(sm, b, wave, lane, r, v);                                         \
+      _Pragma("unroll") for (int k = 0; k < 4; ++k) {                                    \
+        acc[k][r].x = k == ph_ ? 0.f : acc[k][r].x;                                      \
+        acc[k][r].y = k == ph_ ? 0.f : acc[k][r].y;                                      \
+        acc[k][r].z = k == ph_ ? 0.f : acc[k][r].z;                                      \
+      }                                                                                  \
+    }                                                                                    \
+    wave_lds_sync();                                                                     \
+    adj_emit_xf<DX, R>(b, sm, lut, dx, tid, (CZL));                                      \
+    __syncthreads();                                                                     \
+    adj_emit_y<DX, kAdjWaves, StageAll>(a, b, pbase, sm, lut, tid, (CZL), (LAST));       \
+  }
+
+// One voxel plane Z from register set D: z-accumulation, the loads of the
+// plane two ahead into the same registers (when LOAD), then the emission when
+// a z-tile ends.
+#define BSI_ADJ_PLANE(D, Z, LOAD)                                                          \
+  {                                                                                      \
+    const int ph = t & 3;                                                                \
+    const float* ws_ = lut_rot_row(lut, g.dz, oz, ph); /* Bz_((k - ph) & 3): one scalar load */ \
+    _Pragma("unroll") for (int k = 0; k < 4; ++k) {                                      \
+      const float w = ws_[k];                                                            \
+      _Pragma("unroll") for (int r = 0; r < R; ++r) {                                    \
+        acc[k][r].x = fmaf(w, D[r].x, acc[k][r].x);                                      \
+        acc[k][r].y = fmaf(w, D[r].y, acc[k][r].y);                                      \
+        acc[k][r].z = fmaf(w, D[r].z, acc[k][r].z);                                      \
+      }                                                                                  \
+    }                                                                                    \
+    if (LOAD) adj_load<Stream>(ahead, off, D);                                           \
+    ahead += zs;                                                                         \
+    if (++oz == g.dz && (Z) + 1 < b.ze) {                                                \
+      BSI_ADJ_EMIT(t, ph, false)                                                         \
+      oz = 0;                                                                            \
+      ++t;                                                                               \
+    }                                                                                    \
+  }
+
+  // Two register sets, each holding one plane's loads.  The loop is unrolled
+  // over them, and its main part runs only while every plane of the pair and
+  // every plane two ahead exists, so its loads are unconditional: each set
+  // keeps fixed registers, and waiting for one set's loads leaves the other
+  // set's in flight.  (Both sets are first loaded unconditionally, from the
+  // brick's last plane when it is one plane deep, so the loop is entered with
+  // the same loads in flight on every path.)
+  F3 d0[R], d1[R];
+  adj_load<Stream>(plane0, off, d0);
+  adj_load<Stream>(plane0 + (b.ze - b.z0 > 1 ? zs : 0), off, d1);
   int z = b.z0;
-  for (; z + 2 * kAdjAhead <= b.ze; z += kAdjAhead) {
-#pragma unroll
-    for (int j = 0; j < kAdjAhead; ++j) consume(d[j], z + j, true);
+  for (; z + 4 <= b.ze; z += 2) {
+    BSI_ADJ_PLANE(d0, z, true)
+    BSI_ADJ_PLANE(d1, z + 1, true)
   }
-  for (; z < b.ze; z += kAdjAhead) {
-#pragma unroll
-    for (int j = 0; j < kAdjAhead; ++j)
-      if (z + j < b.ze) consume(d[j], z + j, z + j + kAdjAhead < b.ze);
+  for (; z < b.ze; z += 2) {
+    BSI_ADJ_PLANE(d0, z, z + 2 < b.ze)
+    if (z + 1 < b.ze) BSI_ADJ_PLANE(d1, z + 1, z + 3 < b.ze)
   }
-  // the last tile's four planes (the last three are shared with the next brick)
+  // The brick's last four control planes, t .. t + 3 (the last three are
+  // shared with the next brick), in slots (t + n) & 3, in ascending order.
 #pragma unroll 1
-  for (int n = 0; n < 4; ++n) emit0(tz - b.cz0 + n, n == 3);
+  for (int n = 0; n < 4; ++n) BSI_ADJ_EMIT(t + n, (t + n) & 3, n == 3)
+#undef BSI_ADJ_PLANE
+#undef BSI_ADJ_EMIT
 }
 
 // Pass 2 for one control point (cx, cy, cz): fixed-order sum of brick partials.
@@ -504,6 +595,42 @@ __device__ __forceinline__ F3 adj_gather_point(const float* __restrict__ part, c
         s.z += v.z;
       }
   return s;
+}
+
+// Pass 2's workgroups: a wave takes up to 64 control points along x of one
+// control row (cy, cz), so the y- and z-brick spans, and their address terms,
+// are uniform over the wave (scalar).  A workgroup holds kGatherWaves rows.
+constexpr int kGatherWaves = 4;
+constexpr int kGatherThreads = kGatherWaves * kWave;
+
+__host__ __device__ inline int adj_gather_xblocks(const VolGeom& g) { return (g.gx + kWave - 1) / kWave; }
+__host__ __device__ inline int adj_gather_yblocks(const VolGeom& g) {
+  return (g.gy + kGatherWaves - 1) / kGatherWaves;
+}
+__host__ __device__ inline int64_t adj_gather_blocks(const VolGeom& g) {
+  return (int64_t)adj_gather_xblocks(g) * adj_gather_yblocks(g) * g.gz;
+}
+
+// Control point of lane `lane` of wave `wave` of pass-2 workgroup blk
+// (blk < adj_gather_blocks < 2^31); false for a lane past the grid.
+__host__ __device__ inline bool adj_gather_index(const VolGeom& g, int blk, int wave, int lane, int& cx, int& cy,
+                                                 int& cz) {
+  const int nxb = adj_gather_xblocks(g), nyb = adj_gather_yblocks(g);
+  const int xb = blk % nxb;
+  blk /= nxb;
+  cy = (blk % nyb) * kGatherWaves + wave;
+  cz = blk / nyb;
+  cx = xb * kWave + lane;
+  return cy < g.gy && cx < g.gx;
+}
+
+// Workgroup blk of pass 2, thread tid.
+__device__ __forceinline__ void adj_gather_block(const float* __restrict__ part, float* __restrict__ grad,
+                                                 const AdjGeom& a, int blk, int tid) {
+  int cx, cy, cz;
+  if (!adj_gather_index(a.g, blk, uniform(tid / kWave), tid & (kWave - 1), cx, cy, cz)) return;
+  const size_t i = ((size_t)cz * a.g.gy + cy) * a.g.gx + cx;
+  stf3(grad + i * 3, adj_gather_point(part, a, cx, cy, cz));
 }
 
 }  // namespace bsi

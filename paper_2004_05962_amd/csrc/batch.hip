@@ -44,7 +44,7 @@ struct VolDesc {
 enum Pass { kFwd = 0, kAdj1 = 1, kAdj2 = 2 };
 constexpr int kNumClasses = kAdjMaxDX + 1;  // class dx for dx <= kAdjMaxDX, class 0 otherwise
 inline int dx_class(int dx) { return dx <= kAdjMaxDX ? dx : 0; }
-constexpr int kPtThreads = 256;
+constexpr int kPtThreads = kGatherThreads;  // pass 2's workgroup
 #ifndef BSI_BATCH_FWD_TARGET
 #define BSI_BATCH_FWD_TARGET 2048
 #endif
@@ -155,15 +155,7 @@ __global__ __launch_bounds__(kPtThreads) void batch_adj2_kernel(const VolDesc* _
     const int vi = uniform(find_volume(vols, count, item, kAdj2));
     const VolDesc& d = vols[vi];
     const AdjGeom a = d.a;
-    const int64_t n = (int64_t)a.g.gx * a.g.gy * a.g.gz;
-    const int64_t i = (item - d.first[kAdj2]) * kPtThreads + threadIdx.x;
-    if (i < n) {
-      const int cx = (int)(i % a.g.gx);
-      const int64_t r = i / a.g.gx;
-      const int cy = (int)(r % a.g.gy);
-      const int cz = (int)(r / a.g.gy);
-      stf3(d.grad + i * 3, adj_gather_point(d.part, a, cx, cy, cz));
-    }
+    adj_gather_block(d.part, d.grad, a, (int)(item - d.first[kAdj2]), threadIdx.x);
   }
 }
 
@@ -449,6 +441,10 @@ int32_t bsi_batch_create(int32_t count, const int32_t* dims3xN, const int32_t* s
       set_error("volume " + std::to_string(i) + ": " + bsi_last_error());
       return rc;
     }
+    if (adj_gather_blocks(geoms[i]) >= ((int64_t)1 << 31)) {  // a field far beyond device memory
+      set_error("volume " + std::to_string(i) + ": too many control points");
+      return BSI_ERR_UNSUPPORTED;
+    }
   }
   for (int i = 0; i < count; ++i) {
     const VolGeom& g = geoms[i];
@@ -466,7 +462,7 @@ int32_t bsi_batch_create(int32_t count, const int32_t* dims3xN, const int32_t* s
     d.first[kAdj2] = tot[kAdj2];
     tot[kFwd] += (int64_t)d.f.nbx * d.f.nby * d.f.nbz;
     tot[kAdj1] += (int64_t)d.a.x.nb * d.a.y.nb * d.a.z.nb;
-    tot[kAdj2] += ((int64_t)g.gx * g.gy * g.gz + kPtThreads - 1) / kPtThreads;
+    tot[kAdj2] += adj_gather_blocks(g);
   }
   int dev = 0;
   int32_t rc = current_device(&dev);

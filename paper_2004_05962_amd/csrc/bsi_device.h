@@ -15,6 +15,8 @@ constexpr int kMaxSpacing = 64;
 // Basis table for every spacing d in [1, kMaxSpacing]: row (d, o) holds
 // B0..B3(o/d), the weights of Eq. 1 at in-tile offset o.
 constexpr int kLutFloats = 4 * kMaxSpacing * (kMaxSpacing + 1) / 2;
+// Rotated rows (lut_rot_row), stored after the basis table in the same array.
+constexpr int kLutRotFloats = 4 * kLutFloats;
 constexpr int kNumXcd = 8;  // MI355X: 8 accelerator complex dies, 32 CUs each
 
 // 12-byte vector of the three displacement components.  Packed with 4-byte
@@ -64,6 +66,11 @@ __host__ __device__ constexpr int imax(int a, int b) { return a > b ? a : b; }
 
 __device__ __forceinline__ const float* lut_row(const float* lut, int d, int o) {
   return lut + 4 * ((d * (d - 1)) / 2 + o);
+}
+// Row (d, o) rotated by ph: element k is B_((k - ph) & 3)(o/d).  `lut` is the
+// basis table's device pointer; the rotated rows follow it.
+__device__ __forceinline__ const float* lut_rot_row(const float* lut, int d, int o, int ph) {
+  return lut + kLutFloats + 16 * ((d * (d - 1)) / 2 + o) + 4 * ph;
 }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }

@@ -158,6 +158,7 @@ __device__ __forceinline__ void fused_brick(const float* __restrict__ grid, cons
     base[r] = ((ty - b.cy0) * CXM + (tx - b.cx0)) * 3;
   }
   const FusedStage<DX> map = fused_stage_map<DX>(g, b, tid);
+  adj_zero_fpad<DX, R>(sm.adj, wave, lane);
 
   // Q of the 4 control planes of the first z-tile, one plane staged at a time
   int tz = b.cz0;  // z-bricks are whole tiles: b.z0 = tz * dz
@@ -192,7 +193,7 @@ __device__ __forceinline__ void fused_brick(const float* __restrict__ grid, cons
     F3 f[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) f[r] = acc[r][0];
-    adj_emit_x<DX, R>(b, sm.adj, lut, dx, tid, czl, f);
+    adj_emit_x<DX, R>(b, sm.adj, lut, dx, tid, czl, [&](int r) { return f[r]; });
     __syncthreads();
     adj_emit_y<DX, kFusedWaves, StageAll>(a, b, pbase, sm.adj, lut, tid, czl, last);
 #pragma unroll
@@ -243,7 +244,7 @@ __device__ __forceinline__ void fused_brick(const float* __restrict__ grid, cons
       F3 f[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) f[r] = acc[r][0];
-      adj_emit_x<DX, R>(b, sm.adj, lut, dx, tid, tz - b.cz0, f);
+      adj_emit_x<DX, R>(b, sm.adj, lut, dx, tid, tz - b.cz0, [&](int r) { return f[r]; });
       __syncthreads();
       adj_emit_y<DX, kFusedWaves, StageAll>(a, b, pbase, sm.adj, lut, tid, tz - b.cz0, false);
 #pragma unroll

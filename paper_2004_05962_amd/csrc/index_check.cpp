@@ -40,6 +40,11 @@ bool check_adj_brick(const AdjGeom& a, const AdjBrick& b, Check& ck) {
   REQUIRE(b.Cx <= adj_cx_max(dxc), "x window within the H buffer's row");
   REQUIRE(b.Cy - 3 <= kAdjTiles, "y-tiles within one row of tile lanes");
   if (adj_tile_lanes(dxc)) REQUIRE(b.ntx <= kAdjTiles, "x-tiles within one row of tile lanes");
+  if (adj_fpad(dxc) > 0)  // a tile's voxels, read without tests, lie within the row and its zero pads
+    for (int t = 0; t < b.ntx; ++t) {
+      const int xt = (b.cx0 + t) * a.g.dx - b.x0;
+      REQUIRE(xt >= -adj_fpad(dxc) && xt + a.g.dx <= kWave + adj_fpad(dxc), "x-tile within the padded F row");
+    }
   if (adj_stage_all(a)) REQUIRE((size_t)adj_brick_cz(a, b) * a.y.cm * a.x.cm * 3 <= (size_t)kAdjStageFloats,
                                 "staged partials within the LDS stage");
   for (int w = 0; w < kAdjWaves; ++w)
@@ -105,6 +110,23 @@ bool check_adjoint(const AdjGeom& a, BrickCheck brick_check, Check& ck) {
         REQUIRE(meets == (b >= sp.lo && b <= sp.hi), "pass-2 span differs from the bricks meeting the support");
       }
     }
+  // pass 2's workgroups take every control point exactly once
+  {
+    std::vector<unsigned char> hit((size_t)g.gx * g.gy * g.gz, 0);
+    const int64_t nblk = adj_gather_blocks(g);
+    REQUIRE(nblk < ((int64_t)1 << 31), "pass-2 grid above 2^31 workgroups");
+    for (int64_t blk = 0; blk < nblk; ++blk)
+      for (int w = 0; w < kGatherWaves; ++w)
+        for (int l = 0; l < kWave; ++l) {
+          int cx, cy, cz;
+          if (!adj_gather_index(g, (int)blk, w, l, cx, cy, cz)) continue;
+          REQUIRE(0 <= cx && cx < g.gx && 0 <= cy && cy < g.gy && 0 <= cz && cz < g.gz, "pass-2 point off the grid");
+          unsigned char& h = hit[((size_t)cz * g.gy + cy) * g.gx + cx];
+          REQUIRE(h == 0, "pass-2 point taken twice");
+          h = 1;
+        }
+    for (unsigned char h : hit) REQUIRE(h == 1, "pass-2 point never taken");
+  }
   // pass 2: every brick a control point reads holds that point in its window
   for (int cz = 0; cz < g.gz; ++cz)
     for (int cy = 0; cy < g.gy; ++cy)

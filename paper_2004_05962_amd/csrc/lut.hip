@@ -14,7 +14,9 @@
 
 namespace bsi {
 
-static __device__ float g_lut[kLutFloats];
+// The basis table, followed by the same rows rotated for the adjoint's
+// fixed accumulator slots: row (d, o, ph)[k] = B_((k - ph) & 3)(o/d).
+static __device__ float g_lut[kLutFloats + kLutRotFloats];
 static __device__ float g_lerp_lut[kLutFloats];  // rows (h0, h1, g1, 0)
 
 namespace {
@@ -33,7 +35,7 @@ void basis(double u, double b[4]) {
   b[3] = u3 / 6.0;
 }
 
-// Fill both tables on the host (FP64, rounded once to FP32).
+// Fill the tables on the host (FP64, rounded once to FP32).
 void fill_tables(float* basis_tab, float* lerp_tab) {
   for (int d = 1; d <= kMaxSpacing; ++d)
     for (int o = 0; o < d; ++o) {
@@ -41,6 +43,9 @@ void fill_tables(float* basis_tab, float* lerp_tab) {
       basis((double)o / (double)d, b);
       float* row = basis_tab + 4 * ((d * (d - 1)) / 2 + o);
       for (int l = 0; l < 4; ++l) row[l] = (float)b[l];
+      float* rot = basis_tab + kLutFloats + 16 * ((d * (d - 1)) / 2 + o);
+      for (int ph = 0; ph < 4; ++ph)
+        for (int k = 0; k < 4; ++k) rot[4 * ph + k] = (float)b[(k - ph) & 3];
       float* lr = lerp_tab + 4 * ((d * (d - 1)) / 2 + o);
       lr[0] = (float)(b[1] / (b[0] + b[1]));
       lr[1] = (float)(b[3] / (b[2] + b[3]));
@@ -50,7 +55,7 @@ void fill_tables(float* basis_tab, float* lerp_tab) {
 }
 
 int32_t upload(int dev) {
-  static float host[kLutFloats], lerp_host[kLutFloats];
+  static float host[kLutFloats + kLutRotFloats], lerp_host[kLutFloats];
   fill_tables(host, lerp_host);
   // Upload with plain blocking copies, then resolve this device's addresses.
   hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(g_lut), host, sizeof(host), 0, hipMemcpyHostToDevice);
