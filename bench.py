@@ -353,7 +353,7 @@ def run_extras(torch, bsi, workloads):
     t_sep = median(time_events(torch, plan.run_separate, 20))
     ex["batched_32_volumes"] = {"voxels": vox, "graph_ms": round(t_graph, 4), "separate_ms": round(t_sep, 4),
                                 "speedup": round(t_sep / t_graph, 3), "graph_gvoxel_s": round(vox / t_graph / 1e6, 2),
-                                "schedule": chosen, "schedules": nsched}
+                                "schedule": chosen, "schedules": nsched, "schedule_knobs": plan.describe()}
     log("batched:", ex["batched_32_volumes"])
     plan.close()
     del grids, dfields, fields, grads

@@ -273,18 +273,30 @@ int32_t bsi_batch_create(int32_t count, const int32_t* dims3xN, const int32_t* s
 int32_t bsi_batch_bind(bsi_batch* plan, const float* const* grids, float* const* fields,
                        const float* const* dfields, float* const* grid_grads);
 
-/* Time the candidate schedules (persistent grid size, work order) on `stream`
-   with the bound buffers (the outputs are written while timing) and keep the
-   fastest.  Drops a captured graph.  The choice is stored in the JSON file
-   named by the environment variable BSI_TUNE_CACHE (if set) and read back by
-   later plans with the same geometry.  BSI_FORCE_CONFIG=<index> skips timing;
-   an index that is not a valid schedule is rejected with INVALID_ARG (here and
-   in bsi_batch_create).  Synchronises the plan's device.  Schedules never
-   change result bits. */
+/* Choose the plan's schedule by timing it on `stream` with the bound buffers
+   (the outputs are written while timing).  A schedule sets eight knobs: the
+   forward's workgroup shape (rows x 64-voxel strips: 4x1, 2x2, 8x1), its
+   items per volume (z split target 512, 2048, 8192), the persistent grid of
+   each pass in workgroups per CU (forward 0/2/4/8, pass 1 0/1/2/3, pass 2 0/8;
+   0 = one workgroup per item), the number of streams the pass-1 launches
+   spread over (1, 2, 4), whether the forward runs beside the adjoint or before
+   it, and whether the forward's stores are ordinary or non-temporal.  The search is a coordinate descent from the current schedule, each
+   candidate timed as the median of 5 runs after a warm-up.  Drops a captured
+   graph.  The choice is stored in the JSON file named by the environment
+   variable BSI_TUNE_CACHE (if set) and read back by later plans with the same
+   geometry; BSI_FORCE_CONFIG=<index> skips timing, and an index outside
+   [0, count) (see bsi_batch_config) is rejected with INVALID_ARG, here and in
+   bsi_batch_create.  BSI_TUNE_VERBOSE (set) prints each timing to stderr.
+   Synchronises the plan's device.  No schedule changes a result bit. */
 int32_t bsi_batch_tune(bsi_batch* plan, hipStream_t stream);
 
-/* Index of the schedule the plan uses, and the number of candidates. */
+/* Index of the schedule the plan uses, and the number of schedules. */
 int32_t bsi_batch_config(const bsi_batch* plan, int32_t* index, int32_t* count);
+
+/* The plan's schedule as text ("fwd_tile=4x1 fwd_items=2048 ..."), written
+   NUL-terminated into buf (host, len bytes; truncated to fit).
+   Errors: INVALID_ARG (null plan or buffer, len < 1). */
+int32_t bsi_batch_describe(const bsi_batch* plan, char* buf, int32_t len);
 
 /* Enqueue the persistent forward and adjoint kernels directly on `stream`. */
 int32_t bsi_batch_run(bsi_batch* plan, hipStream_t stream);

@@ -9,7 +9,7 @@ package only marshals arguments.  PyTorch provides device memory and streams.
 from . import _lib
 from ._lib import (BSIError, bsi_adjoint, bsi_adjoint_noalloc, bsi_adjoint_general, bsi_adjoint_general_workspace_size,
                    bsi_adjoint_partials, bsi_adjoint_reduce, bsi_adjoint_workspace_size, bsi_batch_bind,
-                   bsi_batch_capture, bsi_batch_config, bsi_batch_create, bsi_batch_destroy,
+                   bsi_batch_capture, bsi_batch_config, bsi_batch_create, bsi_batch_describe, bsi_batch_destroy,
                    bsi_batch_launch, bsi_batch_run, bsi_batch_run_separate, bsi_batch_tune,
                    bsi_descent_step, bsi_forward, bsi_forward_general, bsi_forward_lerp,
                    bsi_forward_scalar, bsi_general_grid_dims, bsi_grid_dims, bsi_last_error, bsi_ssd_fused,

@@ -30,7 +30,7 @@ EXPORTS = (
     "bsi_adjoint", "bsi_adjoint_partials", "bsi_adjoint_reduce", "bsi_adjoint_noalloc", "bsi_general_grid_dims",
     "bsi_forward_general", "bsi_adjoint_general_workspace_size", "bsi_adjoint_general", "bsi_warp", "bsi_ssd_workspace_size", "bsi_ssd_grad", "bsi_ssd_fused_workspace_size", "bsi_ssd_fused",
     "bsi_descent_step",
-    "bsi_batch_create", "bsi_batch_bind", "bsi_batch_tune", "bsi_batch_config", "bsi_batch_run",
+    "bsi_batch_create", "bsi_batch_bind", "bsi_batch_tune", "bsi_batch_config", "bsi_batch_describe", "bsi_batch_run",
     "bsi_batch_run_separate", "bsi_batch_capture", "bsi_batch_launch", "bsi_batch_destroy",
 )
 
@@ -84,6 +84,7 @@ def lib():
                             ctypes.POINTER(_VP)], i32),
         "bsi_batch_tune": ([_VP, _VP], i32),
         "bsi_batch_config": ([_VP, p3, p3], i32),
+        "bsi_batch_describe": ([_VP, ctypes.c_char_p, i32], i32),
         "bsi_batch_run": ([_VP, _VP], i32),
         "bsi_batch_run_separate": ([_VP, _VP], i32),
         "bsi_batch_capture": ([_VP, _VP], i32),
@@ -407,6 +408,12 @@ def bsi_batch_config(plan):
     i, n = ctypes.c_int32(), ctypes.c_int32()
     _check(lib().bsi_batch_config(plan, ctypes.byref(i), ctypes.byref(n)))
     return int(i.value), int(n.value)
+
+
+def bsi_batch_describe(plan):
+    buf = ctypes.create_string_buffer(512)
+    _check(lib().bsi_batch_describe(plan, buf, 512))
+    return buf.value.decode()
 
 
 def bsi_batch_run(plan, stream=None):

@@ -1,7 +1,7 @@
 """Batched forward + adjoint of many volumes in persistent launches (one HIP graph).
 
 Thin owner of a ``bsi_batch`` plan: create (geometry), bind (device buffers),
-tune (schedule chosen by timing and persisted in BSI_TUNE_CACHE), capture, launch.
+tune (schedule of seven knobs chosen by timing, persisted in BSI_TUNE_CACHE), capture, launch.
 """
 from . import _lib
 
@@ -23,6 +23,9 @@ class BatchPlan:
 
     def config(self):
         return _lib.bsi_batch_config(self._plan)
+
+    def describe(self):
+        return _lib.bsi_batch_describe(self._plan)
 
     def run(self, stream=None):
         _lib.bsi_batch_run(self._plan, stream)

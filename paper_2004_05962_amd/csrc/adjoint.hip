@@ -39,14 +39,24 @@ AdjAxis make_axis(int n, int d, int u, int k) {
 }
 }  // namespace
 
+#ifndef BSI_ADJ_FIT
+#define BSI_ADJ_FIT 1
+#endif
+
 // Bricks of pass 1: kAdjBX voxels (one per lane) by kAdjBY rows by whole
-// z-tiles, about kAdjTargetZ planes deep (at least one tile).
+// z-tiles, about kAdjTargetZ planes deep (at least one tile).  Where fewer
+// tiles, but at least half as many, let a brick's whole window of partials fit
+// the LDS stage, the brick takes that depth: its partials are then stored
+// after its last load instead of one plane at a time between its loads.
 AdjGeom make_adj_geom(const VolGeom& g) {
   AdjGeom a;
   a.g = g;
   a.x = make_axis(g.nx, g.dx, 1, kAdjBX);
   a.y = make_axis(g.ny, g.dy, 1, kAdjBY);
-  const int kz = kAdjTargetZ / g.dz > 0 ? kAdjTargetZ / g.dz : 1;
+  int kz = kAdjTargetZ / g.dz > 0 ? kAdjTargetZ / g.dz : 1;
+  const int kfit = kAdjStageFloats / (a.y.cm * a.x.cm * 3) - 3;  // deepest brick whose window fits
+  if (BSI_ADJ_FIT == 1 && kfit < kz && 2 * kfit >= kz) kz = kfit;
+  if (BSI_ADJ_FIT == 2 && kfit < kz && kfit >= 1) kz = kfit;
   a.z = make_axis(g.nz, g.dz, g.dz, kz);
   return a;
 }

@@ -6,8 +6,10 @@
 // workgroup walks a static slice of the concatenated work list and runs the
 // same per-wave / per-brick / per-point routines as the single-volume kernels,
 // so every volume's output is bit-identical to bsi_forward / bsi_adjoint.
-// Schedules (persistent grid size, slice order) are chosen by timing and never
-// change the arithmetic.
+// The schedule (forward workgroup shape and z split, persistent grid sizes of
+// each pass, how many streams the pass-1 classes spread over, whether the
+// forward runs beside the adjoint) is chosen by timing and never changes the
+// arithmetic.
 //
 // Graph shape: the forward (grid -> field) and the adjoint (dfield -> grad) are
 // independent, so they run as parallel branches (fork/join with events); the
@@ -45,28 +47,73 @@ enum Pass { kFwd = 0, kAdj1 = 1, kAdj2 = 2 };
 constexpr int kNumClasses = kAdjMaxDX + 1;  // class dx for dx <= kAdjMaxDX, class 0 otherwise
 inline int dx_class(int dx) { return dx <= kAdjMaxDX ? dx : 0; }
 constexpr int kPtThreads = kGatherThreads;  // pass 2's workgroup
-#ifndef BSI_BATCH_FWD_TARGET
-#define BSI_BATCH_FWD_TARGET 2048
-#endif
-constexpr long kBatchFwdTarget = BSI_BATCH_FWD_TARGET;  // forward items per volume (z split)
 constexpr int kClassStreams = 3;  // pass-1 class launches run on the caller's stream and these
 
-struct Schedule {
-  int fwd_per_cu;  // persistent workgroups per CU (0 = one workgroup per item)
-  int adj_per_cu;
-  int pts_per_cu;
-  int chunked;     // 0: item = wg + k * G;  1: contiguous slices per workgroup
-};
+// ---- schedule knobs: each a small table of values, none changes a result bit
+enum Knob { kKFwdShape, kKFwdItems, kKFwdPerCu, kKAdjPerCu, kKPtsPerCu, kKBranches, kKBeside, kKFwdNT, kNumKnobs };
+// forward workgroup shapes R x S (R rows of S 64-voxel strips: FwdTile<R, S, 1>)
+constexpr int kNumFwdShapes = 3;
+static const char* const kFwdShapeName[kNumFwdShapes] = {"4x1", "2x2", "8x1"};
+static const int kFwdShapeWidth[kNumFwdShapes] = {64, 128, 64};
+static const int kFwdShapeRows[kNumFwdShapes] = {4, 2, 8};
+static const int kFwdItems[] = {512, 2048, 8192};  // forward items per volume (the z split aims at this)
+static const int kFwdPerCu[] = {0, 2, 4, 8};       // forward workgroups per CU (0: one per item)
+static const int kAdjPerCu[] = {0, 1, 2, 3};       // pass-1 workgroups per CU (0: one per brick)
+static const int kPtsPerCu[] = {0, 8};             // pass-2 workgroups per CU (0: one per block)
+static const int kBranches[] = {1, 2, 4};          // streams the pass-1 classes are spread over
+static const int kBeside[] = {1, 0};               // 1: forward beside the adjoint; 0: forward first
+static const int kFwdNT[] = {0, 1};                // forward stores: 0 ordinary, 1 non-temporal
+static const int kKnobSize[kNumKnobs] = {kNumFwdShapes, 3, 4, 4, 2, 3, 2, 2};
+static const char* const kKnobName[kNumKnobs] = {"fwd_tile",      "fwd_items",     "fwd_wg_per_cu",
+                                                 "adj_wg_per_cu", "pts_wg_per_cu", "pass1_streams",
+                                                 "fwd_beside",    "fwd_nt_stores"};
+static_assert(kClassStreams + 1 >= 4, "the largest pass1_streams value");
 
-// Candidate schedules; index 0 is the non-persistent reference.  (Persistent
-// grids of 1-2 workgroups per CU for pass 1, and contiguous slices, measured
-// 8-50% slower once the pass-1 classes run concurrently, and are not offered.)
-static const Schedule kSchedules[] = {
-    {0, 0, 0, 0},
-    {4, 2, 8, 0},
+struct BatchConfig {
+  int k[kNumKnobs];  // value index of each knob
 };
-constexpr int kNumSchedules = sizeof(kSchedules) / sizeof(kSchedules[0]);
-constexpr int kDefaultSchedule = 0;
+// The starting point of the search: 4x1 forward, 2048 items per volume, one
+// workgroup per item in every pass, pass 1 over 4 streams, forward beside the
+// adjoint with ordinary stores.
+static const BatchConfig kDefaultConfig = {{0, 1, 0, 0, 0, 2, 0, 0}};
+
+int config_count() {
+  int n = 1;
+  for (int i = 0; i < kNumKnobs; ++i) n *= kKnobSize[i];
+  return n;
+}
+int encode_config(const BatchConfig& c) {
+  int v = 0;
+  for (int i = kNumKnobs - 1; i >= 0; --i) v = v * kKnobSize[i] + c.k[i];
+  return v;
+}
+BatchConfig decode_config(int v) {
+  BatchConfig c;
+  for (int i = 0; i < kNumKnobs; ++i) {
+    c.k[i] = v % kKnobSize[i];
+    v /= kKnobSize[i];
+  }
+  return c;
+}
+std::string describe_config(const BatchConfig& c) {
+  std::string out;
+  for (int i = 0; i < kNumKnobs; ++i) {
+    if (i) out += ' ';
+    out += kKnobName[i];
+    out += '=';
+    switch (i) {
+      case kKFwdShape: out += kFwdShapeName[c.k[i]]; break;
+      case kKFwdItems: out += std::to_string(kFwdItems[c.k[i]]); break;
+      case kKFwdPerCu: out += std::to_string(kFwdPerCu[c.k[i]]); break;
+      case kKAdjPerCu: out += std::to_string(kAdjPerCu[c.k[i]]); break;
+      case kKPtsPerCu: out += std::to_string(kPtsPerCu[c.k[i]]); break;
+      case kKBranches: out += std::to_string(kBranches[c.k[i]]); break;
+      case kKBeside: out += std::to_string(kBeside[c.k[i]]); break;
+      default: out += std::to_string(kFwdNT[c.k[i]]); break;
+    }
+  }
+  return out;
+}
 
 __device__ __forceinline__ int find_volume(const VolDesc* __restrict__ v, int count, int64_t item, int pass) {
   int lo = 0, hi = count - 1;  // last volume whose first item <= item
@@ -78,34 +125,17 @@ __device__ __forceinline__ int find_volume(const VolDesc* __restrict__ v, int co
   return lo;
 }
 
-// Static slice of [0, total) for this workgroup.
-struct Slice {
-  int64_t begin, end, step;
-};
+// The items of this workgroup (batch_items).
+#define BSI_BATCH_ITEMS(item, total, Persistent)                                            \
+  for (ItemRange r_ = batch_items(blockIdx.x, gridDim.x, (total), (Persistent)); r_.first < (total); \
+       r_.first += r_.step)                                                                \
+    if (const int64_t item = r_.first; true)
 
-__device__ __forceinline__ Slice make_slice(int64_t total, int chunked) {
-  const int64_t G = gridDim.x;
-  const int64_t w = xcd_remap(blockIdx.x, gridDim.x);
-  Slice s;
-  if (chunked) {
-    const int64_t per = (total + G - 1) / G;
-    s.begin = w * per;
-    s.end = s.begin + per < total ? s.begin + per : total;
-    s.step = 1;
-  } else {
-    s.begin = w;
-    s.end = total;
-    s.step = G;
-  }
-  return s;
-}
-
-__global__ __launch_bounds__(kFwdThreads) void batch_fwd_kernel(const VolDesc* __restrict__ vols, int count,
-                                                                 int64_t total, int chunked,
-                                                                 const float* __restrict__ lut) {
-  __shared__ FwdSmem<3> sm;
-  const Slice s = make_slice(total, chunked);
-  for (int64_t item = s.begin; item < s.end; item += s.step) {
+template <class T, bool NT, bool Persistent>
+__global__ __launch_bounds__(T::threads) void batch_fwd_kernel(const VolDesc* __restrict__ vols, int count,
+                                                               int64_t total, const float* __restrict__ lut) {
+  __shared__ FwdSmem<3, T> sm;
+  BSI_BATCH_ITEMS(item, total, Persistent) {
     const int vi = uniform(find_volume(vols, count, item, kFwd));
     const VolDesc& d = vols[vi];
     const VolGeom g = d.a.g;
@@ -117,24 +147,19 @@ __global__ __launch_bounds__(kFwdThreads) void batch_fwd_kernel(const VolDesc* _
     const int bz = id / L.nby;
     const int z0 = bz * L.zchunk;
     const int z1 = min(g.nz, z0 + L.zchunk);
-    // ordinary stores throughout: beside the adjoint classes in the graph they
-    // measured faster than non-temporal (1.31-1.36 against 1.35-1.38 ms for
-    // the 32-volume graph) and than edge stores
-    fwd_block<3, FwdTileDefault, false, true>(d.grid, d.field, g, lut, bx * kWave, by * kFwdRows, z0, z1, sm,
-                                              threadIdx.x);
+    fwd_block<3, T, NT, !NT>(as_global(d.grid), as_global(d.field), g, lut, bx * T::width, by * T::rows, z0, z1, sm,
+                             threadIdx.x);
   }
 }
 
 // Pass 1 over the volumes of one x-spacing class (DX = 1..kAdjMaxDX, or 0 for
 // the generic path), each class with its own descriptor sub-table, so every
 // launch keeps the register footprint of its own specialisation.
-template <int DX>
-__global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(BSI_ADJ_WPE))) void batch_adj1_kernel(const VolDesc* __restrict__ vols, int count,
-                                                                   int64_t total, int chunked,
-                                                                   const float* __restrict__ lut) {
+template <int DX, bool Persistent>
+__global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(BSI_ADJ_WPE))) void batch_adj1_kernel(
+    const VolDesc* __restrict__ vols, int count, int64_t total, const float* __restrict__ lut) {
   __shared__ AdjSmem<DX> sm;
-  const Slice s = make_slice(total, chunked);
-  for (int64_t item = s.begin; item < s.end; item += s.step) {
+  BSI_BATCH_ITEMS(item, total, Persistent) {
     const int vi = uniform(find_volume(vols, count, item, kAdj1));
     const VolDesc& d = vols[vi];
     const AdjGeom a = d.a;
@@ -142,20 +167,20 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(BSI
     // streaming loads measured 2-5% slower here
     const int brick = (int)(item - d.first[kAdj1]);
     if (adj_stage_all(a))
-      adj_brick<DX, false, true>(d.dfield, d.part, a, lut, brick, sm, threadIdx.x);
+      adj_brick<DX, false, true>(as_global(d.dfield), as_global(d.part), a, lut, brick, sm, threadIdx.x);
     else
-      adj_brick<DX, false, false>(d.dfield, d.part, a, lut, brick, sm, threadIdx.x);
+      adj_brick<DX, false, false>(as_global(d.dfield), as_global(d.part), a, lut, brick, sm, threadIdx.x);
   }
 }
 
+template <bool Persistent>
 __global__ __launch_bounds__(kPtThreads) void batch_adj2_kernel(const VolDesc* __restrict__ vols, int count,
-                                                                 int64_t total, int chunked) {
-  const Slice s = make_slice(total, chunked);
-  for (int64_t item = s.begin; item < s.end; item += s.step) {
+                                                                 int64_t total) {
+  BSI_BATCH_ITEMS(item, total, Persistent) {
     const int vi = uniform(find_volume(vols, count, item, kAdj2));
     const VolDesc& d = vols[vi];
     const AdjGeom a = d.a;
-    adj_gather_block(d.part, d.grad, a, (int)(item - d.first[kAdj2]), threadIdx.x);
+    adj_gather_block(as_global(d.part), as_global(d.grad), a, (int)(item - d.first[kAdj2]), threadIdx.x);
   }
 }
 
@@ -180,7 +205,8 @@ struct bsi_batch {
   float* d_part = nullptr;
   const float* lut = nullptr;
   bool has_fwd = false, has_adj = false;
-  int schedule = kDefaultSchedule;
+  BatchConfig cfg = kDefaultConfig;
+  int layout_shape = -1, layout_items = -1;  // forward shape and z split the descriptors hold
   std::string key;
   hipStream_t side = nullptr;  // second branch (forward) of run / capture
   hipEvent_t fork = nullptr, join = nullptr;
@@ -222,52 +248,84 @@ void drop_graph(bsi_batch* p) {
   p->graph = nullptr;
 }
 
+// Workgroups of a pass: one per item, or a persistent grid of per_cu per CU.
+// A pass of 2^31 items or more always runs persistent (on the largest grid).
+int64_t pass_grid(const bsi_batch* p, int64_t total, int per_cu) {
+  int64_t grid = per_cu == 0 ? total : std::min<int64_t>(total, (int64_t)per_cu * p->cus);
+  return std::min<int64_t>(grid, 0x7fffffff);
+}
+bool pass_persistent(int64_t total, int per_cu) { return per_cu > 0 || total > 0x7fffffff; }
+
+template <class T>
+void launch_fwd_shape(const bsi_batch* p, int64_t total, int per_cu, bool nt, hipStream_t s) {
+  const dim3 gd((unsigned)pass_grid(p, total, per_cu)), bd(T::threads);
+  const bool pers = pass_persistent(total, per_cu);
+  if (!pers && !nt)
+    hipLaunchKernelGGL((batch_fwd_kernel<T, false, false>), gd, bd, 0, s, p->d_desc, p->count, total, p->lut);
+  else if (!pers)
+    hipLaunchKernelGGL((batch_fwd_kernel<T, true, false>), gd, bd, 0, s, p->d_desc, p->count, total, p->lut);
+  else if (!nt)
+    hipLaunchKernelGGL((batch_fwd_kernel<T, false, true>), gd, bd, 0, s, p->d_desc, p->count, total, p->lut);
+  else
+    hipLaunchKernelGGL((batch_fwd_kernel<T, true, true>), gd, bd, 0, s, p->d_desc, p->count, total, p->lut);
+}
+
 hipError_t launch_pass(bsi_batch* p, int pass, hipStream_t s) {
-  const Schedule& sc = kSchedules[p->schedule];
   const int64_t total = p->total[pass];
   if (total == 0) return hipSuccess;
-  const int per_cu = pass == kFwd ? sc.fwd_per_cu : pass == kAdj1 ? sc.adj_per_cu : sc.pts_per_cu;
-  int64_t grid = per_cu == 0 ? total : std::min<int64_t>(total, (int64_t)per_cu * p->cus);
-  if (grid > 0x7fffffff) grid = 0x7fffffff;
-  const int chunked = per_cu == 0 ? 0 : sc.chunked;
   if (pass == kFwd) {
-    hipLaunchKernelGGL(batch_fwd_kernel, dim3((unsigned)grid), dim3(kFwdThreads), 0, s, p->d_desc,
-                       p->count, total, chunked, p->lut);
+    const int per_cu = kFwdPerCu[p->cfg.k[kKFwdPerCu]];
+    const bool nt = kFwdNT[p->cfg.k[kKFwdNT]] != 0;
+    static_assert(kNumFwdShapes == 3, "one case per forward shape");
+    switch (p->cfg.k[kKFwdShape]) {
+      case 0: launch_fwd_shape<FwdTile<4, 1, 1>>(p, total, per_cu, nt, s); break;
+      case 1: launch_fwd_shape<FwdTile<2, 2, 1>>(p, total, per_cu, nt, s); break;
+      default: launch_fwd_shape<FwdTile<8, 1, 1>>(p, total, per_cu, nt, s); break;
+    }
   } else if (pass == kAdj1) {
     return hipErrorInvalidValue;  // pass 1 is launched per class (launch_adj1_class)
   } else {
-    hipLaunchKernelGGL(batch_adj2_kernel, dim3((unsigned)grid), dim3(kPtThreads), 0, s, p->d_desc, p->count,
-                       total, chunked);
+    const int per_cu = kPtsPerCu[p->cfg.k[kKPtsPerCu]];
+    const dim3 gd((unsigned)pass_grid(p, total, per_cu)), bd(kPtThreads);
+    if (!pass_persistent(total, per_cu))
+      hipLaunchKernelGGL(batch_adj2_kernel<false>, gd, bd, 0, s, p->d_desc, p->count, total);
+    else
+      hipLaunchKernelGGL(batch_adj2_kernel<true>, gd, bd, 0, s, p->d_desc, p->count, total);
   }
   return hipGetLastError();
 }
 
+template <int DX>
+void launch_adj1_dx(const bsi_batch* p, const VolDesc* v, int n, int64_t ct, int per_cu, hipStream_t s) {
+  const dim3 gd((unsigned)pass_grid(p, ct, per_cu)), bd(kAdjThreads);
+  if (!pass_persistent(ct, per_cu))
+    hipLaunchKernelGGL((batch_adj1_kernel<DX, false>), gd, bd, 0, s, v, n, ct, p->lut);
+  else
+    hipLaunchKernelGGL((batch_adj1_kernel<DX, true>), gd, bd, 0, s, v, n, ct, p->lut);
+}
+
 // Adjoint pass 1 over the volumes of x-spacing class c, on stream s.
 hipError_t launch_adj1_class(bsi_batch* p, int c, hipStream_t s) {
-  const Schedule& sc = kSchedules[p->schedule];
   const int n = p->cls_first[c + 1] - p->cls_first[c];
   const int64_t ct = p->cls_total[c];
   if (n == 0 || ct == 0) return hipSuccess;
-  const int per_cu = sc.adj_per_cu;
-  const int chunked = per_cu == 0 ? 0 : sc.chunked;
-  const int64_t cg = per_cu == 0 ? ct : std::min<int64_t>(ct, (int64_t)per_cu * p->cus);
-  const dim3 gd((unsigned)cg), bd(kAdjThreads);
+  const int per_cu = kAdjPerCu[p->cfg.k[kKAdjPerCu]];
   const VolDesc* v = p->d_cls + p->cls_first[c];
   static_assert(kAdjMaxDX == 12, "one case per specialised spacing");
   switch (c) {
-    case 1: hipLaunchKernelGGL(batch_adj1_kernel<1>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
-    case 2: hipLaunchKernelGGL(batch_adj1_kernel<2>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
-    case 3: hipLaunchKernelGGL(batch_adj1_kernel<3>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
-    case 4: hipLaunchKernelGGL(batch_adj1_kernel<4>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
-    case 5: hipLaunchKernelGGL(batch_adj1_kernel<5>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
-    case 6: hipLaunchKernelGGL(batch_adj1_kernel<6>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
-    case 7: hipLaunchKernelGGL(batch_adj1_kernel<7>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
-    case 8: hipLaunchKernelGGL(batch_adj1_kernel<8>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
-    case 9: hipLaunchKernelGGL(batch_adj1_kernel<9>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
-    case 10: hipLaunchKernelGGL(batch_adj1_kernel<10>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
-    case 11: hipLaunchKernelGGL(batch_adj1_kernel<11>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
-    case 12: hipLaunchKernelGGL(batch_adj1_kernel<12>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
-    default: hipLaunchKernelGGL(batch_adj1_kernel<0>, gd, bd, 0, s, v, n, ct, chunked, p->lut); break;
+    case 1: launch_adj1_dx<1>(p, v, n, ct, per_cu, s); break;
+    case 2: launch_adj1_dx<2>(p, v, n, ct, per_cu, s); break;
+    case 3: launch_adj1_dx<3>(p, v, n, ct, per_cu, s); break;
+    case 4: launch_adj1_dx<4>(p, v, n, ct, per_cu, s); break;
+    case 5: launch_adj1_dx<5>(p, v, n, ct, per_cu, s); break;
+    case 6: launch_adj1_dx<6>(p, v, n, ct, per_cu, s); break;
+    case 7: launch_adj1_dx<7>(p, v, n, ct, per_cu, s); break;
+    case 8: launch_adj1_dx<8>(p, v, n, ct, per_cu, s); break;
+    case 9: launch_adj1_dx<9>(p, v, n, ct, per_cu, s); break;
+    case 10: launch_adj1_dx<10>(p, v, n, ct, per_cu, s); break;
+    case 11: launch_adj1_dx<11>(p, v, n, ct, per_cu, s); break;
+    case 12: launch_adj1_dx<12>(p, v, n, ct, per_cu, s); break;
+    default: launch_adj1_dx<0>(p, v, n, ct, per_cu, s); break;
   }
   return hipGetLastError();
 }
@@ -283,7 +341,7 @@ int32_t enqueue_adjoint(bsi_batch* p, hipStream_t s) {
   for (int c = 0; c < kNumClasses; ++c)
     if (p->cls_total[c] > 0) order[used++] = c;
   std::stable_sort(order, order + used, [p](int a, int b) { return p->cls_total[a] > p->cls_total[b]; });
-  const int branches = std::min(used, kClassStreams + 1);
+  const int branches = std::min(used, kBranches[p->cfg.k[kKBranches]]);
   for (int j = 0; j + 1 < branches; ++j)
     if ((e = hipStreamWaitEvent(p->cls_side[j], p->fork, 0)) != hipSuccess) return hip_fail(e, "forking pass 1");
   for (int k = 0; k < used; ++k) {
@@ -299,21 +357,59 @@ int32_t enqueue_adjoint(bsi_batch* p, hipStream_t s) {
   return BSI_OK;
 }
 
-// Forward on the side stream, adjoint on `s`, joined back into `s`.
+// Forward and adjoint on `s`: with fwd_beside the forward runs on the side
+// stream beside the adjoint and is joined back into `s`, otherwise first.
 int32_t enqueue(bsi_batch* p, hipStream_t s) {
   hipError_t e;
+  const bool beside = p->has_fwd && p->has_adj && kBeside[p->cfg.k[kKBeside]];
+  if (p->has_fwd && !beside && (e = launch_pass(p, kFwd, s)) != hipSuccess)
+    return hip_fail(e, "launching the batched forward");
   if (p->has_adj && (e = hipEventRecord(p->fork, s)) != hipSuccess) return hip_fail(e, "recording the fork event");
-  if (p->has_fwd && p->has_adj) {
+  if (beside) {
     if ((e = hipStreamWaitEvent(p->side, p->fork, 0)) != hipSuccess) return hip_fail(e, "forking");
     if ((e = launch_pass(p, kFwd, p->side)) != hipSuccess) return hip_fail(e, "launching the batched forward");
+  }
+  if (p->has_adj) {
     const int32_t rc = enqueue_adjoint(p, s);
     if (rc) return rc;
+  }
+  if (beside) {
     if ((e = hipEventRecord(p->join, p->side)) != hipSuccess) return hip_fail(e, "recording the join event");
     if ((e = hipStreamWaitEvent(s, p->join, 0)) != hipSuccess) return hip_fail(e, "joining");
-    return BSI_OK;
   }
-  if (p->has_fwd && (e = launch_pass(p, kFwd, s)) != hipSuccess) return hip_fail(e, "launching the batched forward");
-  if (p->has_adj) return enqueue_adjoint(p, s);
+  return BSI_OK;
+}
+
+// The forward's work items for the plan's forward shape and z split (host
+// descriptors only); true when they changed.
+bool layout_forward(bsi_batch* p) {
+  const int sh = p->cfg.k[kKFwdShape], it = p->cfg.k[kKFwdItems];
+  if (sh == p->layout_shape && it == p->layout_items) return false;
+  int64_t tot = 0;
+  for (VolDesc& d : p->host) {
+    d.f = make_fwd_launch(d.a.g, kFwdItems[it], kFwdShapeWidth[sh], kFwdShapeRows[sh]);
+    d.first[kFwd] = tot;
+    tot += (int64_t)d.f.nbx * d.f.nby * d.f.nbz;
+  }
+  p->total[kFwd] = tot;
+  p->layout_shape = sh;
+  p->layout_items = it;
+  return true;
+}
+
+int32_t upload_tables(bsi_batch* p) {
+  hipError_t e = hipMemcpy(p->d_desc, p->host.data(), sizeof(VolDesc) * p->host.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "uploading the descriptor table");
+  e = hipMemcpy(p->d_cls, p->cls_host.data(), sizeof(VolDesc) * p->cls_host.size(), hipMemcpyHostToDevice);
+  return e == hipSuccess ? BSI_OK : hip_fail(e, "uploading the class descriptor table");
+}
+
+// Switch the plan to configuration c.  Callers quiesce first: the forward's
+// descriptors may be rewritten.  Drops a captured graph.
+int32_t set_config(bsi_batch* p, const BatchConfig& c) {
+  p->cfg = c;
+  drop_graph(p);
+  if (layout_forward(p) && (p->has_fwd || p->has_adj)) return upload_tables(p);
   return BSI_OK;
 }
 
@@ -391,11 +487,11 @@ void cache_store(const char* path, const std::string& key, int value) {
   std::rename(tmp.c_str(), path);
 }
 
-// A schedule index in [0, kNumSchedules), written as a plain decimal number.
-bool parse_schedule(const char* text, int* out) {
+// A configuration index in [0, config_count()), written as a plain decimal number.
+bool parse_config(const char* text, int* out) {
   char* end = nullptr;
   const long v = std::strtol(text, &end, 10);
-  if (end == text || *end != '\0' || v < 0 || v >= kNumSchedules) return false;
+  if (end == text || *end != '\0' || v < 0 || v >= config_count()) return false;
   *out = (int)v;
   return true;
 }
@@ -415,7 +511,8 @@ std::string plan_key(const bsi_batch* p) {
     mix(d.a.g.dx); mix(d.a.g.dy); mix(d.a.g.dz);
   }
   char buf[64];
-  std::snprintf(buf, sizeof(buf), "gfx950-cu%d-%016llx", p->cus, (unsigned long long)h);
+  // "k2": the knob tables of this version (an index means another schedule under other tables)
+  std::snprintf(buf, sizeof(buf), "k2-gfx950-cu%d-%016llx", p->cus, (unsigned long long)h);
   return buf;
 }
 
@@ -450,17 +547,11 @@ int32_t bsi_batch_create(int32_t count, const int32_t* dims3xN, const int32_t* s
     const VolGeom& g = geoms[i];
     VolDesc& d = host[i];
     std::memset(&d, 0, sizeof(d));
-    d.a = make_adj_geom(g);
-    // Each volume's forward is split in z to about kBatchFwdTarget items:
-    // fewer than a standalone launch needs (the batch fills the GPU), more than
-    // one item per column (short items balance better across the batch).
-    d.f = make_fwd_launch(g, kBatchFwdTarget);
+    d.a = make_adj_geom(g);  // the forward's items are laid out by layout_forward
     off[i] = part_floats;
     part_floats += adj_workspace_bytes(d.a) / sizeof(float);
-    d.first[kFwd] = tot[kFwd];
     d.first[kAdj1] = tot[kAdj1];
     d.first[kAdj2] = tot[kAdj2];
-    tot[kFwd] += (int64_t)d.f.nbx * d.f.nby * d.f.nbz;
     tot[kAdj1] += (int64_t)d.a.x.nb * d.a.y.nb * d.a.z.nb;
     tot[kAdj2] += adj_gather_blocks(g);
   }
@@ -502,6 +593,7 @@ int32_t bsi_batch_create(int32_t count, const int32_t* dims3xN, const int32_t* s
     }
   }
   p->cls_first[kNumClasses] = (int)p->cls_host.size();
+
   if (hipMalloc(&p->d_cls, sizeof(VolDesc) * (size_t)count) != hipSuccess) {
     (void)hipGetLastError();
     bsi_batch_destroy(p);
@@ -523,17 +615,18 @@ int32_t bsi_batch_create(int32_t count, const int32_t* dims3xN, const int32_t* s
   p->key = plan_key(p);
   if (const char* force = std::getenv("BSI_FORCE_CONFIG")) {
     int v = -1;
-    if (!parse_schedule(force, &v)) {
+    if (!parse_config(force, &v)) {
       bsi_batch_destroy(p);
-      set_error(std::string("BSI_FORCE_CONFIG=") + force + " is not a schedule index in [0, " +
-                std::to_string(kNumSchedules) + ")");
+      set_error(std::string("BSI_FORCE_CONFIG=") + force + " is not a configuration index in [0, " +
+                std::to_string(config_count()) + ")");
       return BSI_ERR_INVALID_ARG;
     }
-    p->schedule = v;
+    p->cfg = decode_config(v);
   } else if (const char* path = std::getenv("BSI_TUNE_CACHE")) {
     const int v = cache_lookup(path, p->key);
-    if (v >= 0 && v < kNumSchedules) p->schedule = v;
+    if (v >= 0 && v < config_count()) p->cfg = decode_config(v);
   }
+  layout_forward(p);  // nothing is bound yet: the tables are uploaded by bind
   *out = p;
   return BSI_OK;
 }
@@ -577,10 +670,7 @@ int32_t bsi_batch_bind(bsi_batch* p, const float* const* grids, float* const* fi
       }
   }
   drop_graph(p);
-  hipError_t e = hipMemcpy(p->d_desc, p->host.data(), sizeof(VolDesc) * p->host.size(), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return hip_fail(e, "uploading the descriptor table");
-  e = hipMemcpy(p->d_cls, p->cls_host.data(), sizeof(VolDesc) * p->cls_host.size(), hipMemcpyHostToDevice);
-  return e == hipSuccess ? BSI_OK : hip_fail(e, "uploading the class descriptor table");
+  return upload_tables(p);
 }
 
 int32_t bsi_batch_config(const bsi_batch* p, int32_t* index, int32_t* count) {
@@ -589,8 +679,18 @@ int32_t bsi_batch_config(const bsi_batch* p, int32_t* index, int32_t* count) {
     set_error("null argument");
     return BSI_ERR_INVALID_ARG;
   }
-  *index = p->schedule;
-  *count = kNumSchedules;
+  *index = encode_config(p->cfg);
+  *count = config_count();
+  return BSI_OK;
+}
+
+int32_t bsi_batch_describe(const bsi_batch* p, char* buf, int32_t len) {
+  clear_error();
+  if (!p || !buf || len < 1) {
+    set_error("null argument or empty buffer");
+    return BSI_ERR_INVALID_ARG;
+  }
+  std::snprintf(buf, (size_t)len, "%s", describe_config(p->cfg).c_str());
   return BSI_OK;
 }
 
@@ -635,14 +735,12 @@ int32_t bsi_batch_tune(bsi_batch* p, hipStream_t stream) {
   if ((rc = quiesce(p))) return rc;
   if (const char* force = std::getenv("BSI_FORCE_CONFIG")) {
     int v = -1;
-    if (!parse_schedule(force, &v)) {
-      set_error(std::string("BSI_FORCE_CONFIG=") + force + " is not a schedule index in [0, " +
-                std::to_string(kNumSchedules) + ")");
+    if (!parse_config(force, &v)) {
+      set_error(std::string("BSI_FORCE_CONFIG=") + force + " is not a configuration index in [0, " +
+                std::to_string(config_count()) + ")");
       return BSI_ERR_INVALID_ARG;
     }
-    p->schedule = v;
-    drop_graph(p);
-    return BSI_OK;
+    return set_config(p, decode_config(v));
   }
   hipEvent_t t0, t1;
   hipError_t e;
@@ -651,43 +749,75 @@ int32_t bsi_batch_tune(bsi_batch* p, hipStream_t stream) {
     (void)hipEventDestroy(t0);
     return hip_fail(e, "creating a timing event");
   }
-  const int keep = p->schedule;
-  // Two sweeps over the schedules (the first also warms clocks and caches);
-  // each schedule keeps the better of its two medians of 5 timed runs.
-  float sched_ms[kNumSchedules];
-  for (int c = 0; c < kNumSchedules; ++c) sched_ms[c] = 1e30f;
-  for (int sweep = 0; sweep < 2 && rc == BSI_OK; ++sweep)
-    for (int c = 0; c < kNumSchedules && rc == BSI_OK; ++c) {
-      p->schedule = c;
-      if ((rc = enqueue(p, stream))) break;  // warm-up
-      float times[5];
-      for (int r = 0; r < 5 && rc == BSI_OK; ++r) {
-        if ((e = hipEventRecord(t0, stream)) != hipSuccess) {
-          rc = hip_fail(e, "recording a timing event");
-          break;
-        }
-        if ((rc = enqueue(p, stream))) break;
-        if ((e = hipEventRecord(t1, stream)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess ||
-            (e = hipEventElapsedTime(&times[r], t0, t1)) != hipSuccess)
-          rc = hip_fail(e, "timing a schedule");
+  const bool verbose = std::getenv("BSI_TUNE_VERBOSE") != nullptr;
+  // Median of 5 timed runs after one warm-up run.  Every run ends with the
+  // wait for t1 on `stream`, into which all of the plan's branches join, so
+  // the device is idle whenever set_config rewrites the forward's table.
+  auto time_config = [&](const BatchConfig& c, float* ms) -> int32_t {
+    int32_t r = set_config(p, c);
+    if (r) return r;
+    if ((r = enqueue(p, stream))) return r;
+    float times[5];
+    for (int k = 0; k < 5; ++k) {
+      if ((e = hipEventRecord(t0, stream)) != hipSuccess) return hip_fail(e, "recording a timing event");
+      if ((r = enqueue(p, stream))) return r;
+      if ((e = hipEventRecord(t1, stream)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess ||
+          (e = hipEventElapsedTime(&times[k], t0, t1)) != hipSuccess)
+        return hip_fail(e, "timing a configuration");
+    }
+    std::sort(times, times + 5);
+    *ms = times[2];
+    if (verbose) std::fprintf(stderr, "bsi_batch_tune: %-110s %.4f ms\n", describe_config(c).c_str(), *ms);
+    return BSI_OK;
+  };
+  // Coordinate descent from the plan's configuration (the default, or the
+  // cached choice): each knob in turn takes every value with the others held,
+  // and keeps the fastest; sweeps repeat until one changes nothing (at most 3).
+  // The winner is then timed once more beside the starting point, which it
+  // must still beat.
+  const BatchConfig start = p->cfg;
+  std::vector<std::pair<int, float>> seen;  // configuration index, time
+  auto measure = [&](const BatchConfig& c, float* ms) -> int32_t {
+    const int id = encode_config(c);
+    for (const auto& kv : seen)
+      if (kv.first == id) {
+        *ms = kv.second;
+        return BSI_OK;
       }
-      if (rc) break;
-      std::sort(times, times + 5);
-      sched_ms[c] = std::min(sched_ms[c], times[2]);
-    }
-  int best = keep;
-  float best_ms = 1e30f;
-  for (int c = 0; c < kNumSchedules; ++c)
-    if (sched_ms[c] < best_ms) {
-      best_ms = sched_ms[c];
-      best = c;
-    }
+    const int32_t r = time_config(c, ms);
+    if (r == BSI_OK) seen.emplace_back(id, *ms);
+    return r;
+  };
+  BatchConfig best = start;
+  float best_ms = 0.f;
+  rc = measure(best, &best_ms);
+  for (int sweep = 0; sweep < 3 && rc == BSI_OK; ++sweep) {
+    bool changed = false;
+    for (int k = 0; k < kNumKnobs && rc == BSI_OK; ++k)
+      for (int v = 0; v < kKnobSize[k] && rc == BSI_OK; ++v) {
+        if (v == best.k[k]) continue;
+        BatchConfig c = best;
+        c.k[k] = v;
+        float ms = 0.f;
+        if ((rc = measure(c, &ms)) == BSI_OK && ms < best_ms) {
+          best = c;
+          best_ms = ms;
+          changed = true;
+        }
+      }
+    if (!changed) break;
+  }
+  if (rc == BSI_OK && encode_config(best) != encode_config(start)) {
+    float again = 0.f, base = 0.f;
+    if ((rc = time_config(best, &again)) == BSI_OK && (rc = time_config(start, &base)) == BSI_OK && base <= again)
+      best = start;
+  }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
-  p->schedule = rc == BSI_OK ? best : keep;
-  drop_graph(p);
+  const int32_t rc2 = set_config(p, rc == BSI_OK ? best : start);
+  if (rc == BSI_OK) rc = rc2;
   if (rc == BSI_OK)
-    if (const char* path = std::getenv("BSI_TUNE_CACHE")) cache_store(path, p->key, p->schedule);
+    if (const char* path = std::getenv("BSI_TUNE_CACHE")) cache_store(path, p->key, encode_config(p->cfg));
   return rc;
 }
 

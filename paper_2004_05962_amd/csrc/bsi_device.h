@@ -75,13 +75,34 @@ __device__ __forceinline__ const float* lut_rot_row(const float* lut, int d, int
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// A pointer read from memory (not a kernel argument) is taken as a generic
+// pointer, and accesses through it become flat instructions, which also count
+// against the LDS wait counter.  Rebuilt from its bits in the global address
+// space, the accesses derived from it are global ones.
+template <class T>
+__device__ __forceinline__ T* as_global(T* p) {
+  using G = __attribute__((address_space(1))) T;
+  return (T*)(G*)(uintptr_t)p;
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs (id % 8).  Remap so that
 // each XCD receives one contiguous range of logical work items: neighbouring
 // items share control points, which then stay in that XCD's L2.
-__device__ __forceinline__ int xcd_remap(int id, int n) {
+__host__ __device__ __forceinline__ int xcd_remap(int id, int n) {
   const int q = n / kNumXcd, r = n % kNumXcd;
   const int xcd = id % kNumXcd, k = id / kNumXcd;
   return xcd * q + (xcd < r ? xcd : r) + k;
+}
+
+// Work items of workgroup `block` of `grid` over [0, total) in a batched
+// launch: first, first + step, ... while below total.  A persistent grid
+// steps by its size; a grid of one workgroup per item (grid = total) takes
+// its one item and steps past the end.
+struct ItemRange {
+  int64_t first, step;
+};
+__host__ __device__ inline ItemRange batch_items(int block, int grid, int64_t total, bool persistent) {
+  return ItemRange{xcd_remap(block, grid), persistent ? (int64_t)grid : total};
 }
 
 // Order this wave's LDS writes before its following LDS reads (and vice versa):

@@ -154,8 +154,8 @@ bool check_adjoints(const VolGeom& g, Check& ck) { return check_adjoint(make_adj
 
 // The marching forward (fwd_block) with workgroup shape T and C components.
 template <int C, class T>
-bool check_forward_march(const VolGeom& g, Check& ck) {
-  const FwdLaunch L = make_fwd_launch(g, kFwdTargetBlocks, T::width, T::rows);
+bool check_forward_march(const VolGeom& g, Check& ck, long target = kFwdTargetBlocks) {
+  const FwdLaunch L = make_fwd_launch(g, target, T::width, T::rows);
   REQUIRE(L.zchunk % g.dz == 0 && L.zchunk > 0, "z chunks of whole tiles");
   REQUIRE((long)L.nbz * L.zchunk >= g.nz && (long)(L.nbz - 1) * L.zchunk < g.nz, "z chunks cover the volume");
   const size_t cplane = (size_t)g.gx * g.gy * C;
@@ -202,10 +202,20 @@ bool check_forward_span(const VolGeom& g, Check& ck) {
   return true;
 }
 
+// The batched forward's shapes and z-split targets (the schedule knobs).
+bool check_forward_batched(const VolGeom& g, Check& ck) {
+  for (long target : {512L, 2048L, 8192L})
+    if (!(check_forward_march<3, FwdTile<4, 1, 1>>(g, ck, target) &&
+          check_forward_march<3, FwdTile<2, 2, 1>>(g, ck, target) &&
+          check_forward_march<3, FwdTile<8, 1, 1>>(g, ck, target)))
+      return false;
+  return true;
+}
+
 bool check_forward(const VolGeom& g, Check& ck) {
   return check_forward_march<3, FwdTileDefault>(g, ck) && check_forward_march<3, FwdTile<2, 8, 1>>(g, ck) &&
          check_forward_march<1, FwdTile<kFwdRows, 1, 4>>(g, ck) && check_forward_march<1, FwdTileDefault>(g, ck) &&
-         check_forward_span<3>(g, ck) && check_forward_span<1>(g, ck);
+         check_forward_span<3>(g, ck) && check_forward_span<1>(g, ck) && check_forward_batched(g, ck);
 }
 
 }  // namespace
@@ -224,6 +234,35 @@ int bsi_check_indices(const int32_t dims[3], const int32_t spacing[3], char* msg
   }
   Check ck;
   check_adjoints(g, ck) && check_forward(g, ck);
+  std::snprintf(msg, msglen, "%s", ck.msg.c_str());
+  return ck.ok ? 0 : 1;
+}
+
+// The batched kernels' item loops (batch_items): over several totals and
+// grids, one workgroup per item and persistent, every item is taken exactly
+// once and every workgroup's loop ends within ceil(total / grid) passes.
+int bsi_check_batch_items(char* msg, int msglen) {
+  Check ck;
+  auto run = [&](int64_t total, int grid, bool persistent) -> bool {
+    std::vector<int> hit((size_t)total, 0);
+    const int64_t max_pass = (total + grid - 1) / grid;
+    for (int b = 0; b < grid; ++b) {
+      int64_t passes = 0;
+      for (ItemRange r = batch_items(b, grid, total, persistent); r.first < total; r.first += r.step) {
+        REQUIRE(r.first >= 0, "item below zero");
+        REQUIRE(++passes <= max_pass, "a workgroup's item loop does not end");
+        ++hit[(size_t)r.first];
+      }
+    }
+    for (int h : hit) REQUIRE(h == 1, "an item taken other than once");
+    return true;
+  };
+  for (int64_t total : {1L, 2L, 7L, 8L, 9L, 100L, 1000L, 4097L, 20000L}) {
+    if (!run(total, (int)total, false)) break;
+    for (int grid : {1, 3, 8, 256, 512, 1024})
+      if (grid <= total && !run(total, grid, true)) break;
+    if (!ck.ok) break;
+  }
   std::snprintf(msg, msglen, "%s", ck.msg.c_str());
   return ck.ok ? 0 : 1;
 }

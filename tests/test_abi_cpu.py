@@ -123,6 +123,8 @@ def test_batch_argument_checks():
     assert _call("bsi_batch_create", 1, n(0, 4, 4), n(1, 1, 1), ctypes.byref(plan)) == _lib.BSI_ERR_INVALID_ARG
     assert _call("bsi_batch_run", NULL, NULL) == _lib.BSI_ERR_INVALID_ARG
     assert _call("bsi_batch_launch", NULL, NULL) == _lib.BSI_ERR_INVALID_ARG
+    buf = ctypes.create_string_buffer(16)
+    assert _call("bsi_batch_describe", NULL, buf, 16) == _lib.BSI_ERR_INVALID_ARG
     _call("bsi_batch_destroy", NULL)  # NULL is ignored
 
 

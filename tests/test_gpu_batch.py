@@ -34,6 +34,32 @@ def _outputs(dims, spac):
     return fields, grads
 
 
+def _force(plan, index):
+    os.environ["BSI_FORCE_CONFIG"] = str(index)
+    try:
+        plan.tune()
+    finally:
+        del os.environ["BSI_FORCE_CONFIG"]
+    assert plan.config()[0] == index
+
+
+def _covering_schedules(plan):
+    """Schedule indices that together take every value of every knob (greedy
+    over the whole space, which is enumerated through the plan's own text)."""
+    n = plan.config()[1]
+    items = []
+    for idx in range(n):
+        _force(plan, idx)
+        items.append(set(plan.describe().split()))
+    universe = set().union(*items)
+    chosen, covered = [0], set(items[0])
+    while covered != universe:
+        best = max(range(n), key=lambda i: len(items[i] - covered))
+        chosen.append(best)
+        covered |= items[best]
+    return chosen, universe
+
+
 def test_batched_equals_per_volume_bits(batch):
     dims, spac, vols, grids, dfields = batch
     say("batch: per-volume reference")
@@ -44,17 +70,14 @@ def test_batched_equals_per_volume_bits(batch):
     plan = bsi.BatchPlan(dims, spac)
     f, g = _outputs(dims, spac)
     plan.bind(grids, f, dfields, g)
-    n_sched = plan.config()[1]
-    for sched in range(n_sched):
-        os.environ["BSI_FORCE_CONFIG"] = str(sched)
-        try:
-            plan.tune()
-        finally:
-            del os.environ["BSI_FORCE_CONFIG"]
-        assert plan.config()[0] == sched
+    schedules, universe = _covering_schedules(plan)
+    say("batch: schedules", schedules, "cover", len(universe), "knob values")
+    assert len(universe) == 3 + 3 + 4 + 4 + 2 + 3 + 2 + 2
+    for sched in schedules:
+        _force(plan, sched)
         for t in f + g:
             t.fill_(float("nan"))
-        say("batch: schedule", sched)
+        say("batch: schedule", sched, plan.describe())
         plan.run()
         torch.cuda.synchronize()
         for i in range(len(dims)):
@@ -133,6 +156,7 @@ def test_tune_persists_choice(batch, tmp_path):
         assert list(data.values()) == [chosen]
         again = bsi.BatchPlan(dims[:6], spac[:6])
         assert again.config()[0] == chosen
+        assert again.describe() == plan.describe()
         plan.close()
         again.close()
     finally:
@@ -180,12 +204,14 @@ def test_invalid_forced_schedule_rejected(batch):
     plan = bsi.BatchPlan(dims[:2], spac[:2])
     f, g = _outputs(dims[:2], spac[:2])
     plan.bind(grids[:2], f, dfields[:2], g)
-    os.environ["BSI_FORCE_CONFIG"] = "999"
-    try:
-        with pytest.raises(bsi.BSIError):
-            plan.tune()
-        with pytest.raises(bsi.BSIError):
-            bsi.BatchPlan(dims[:2], spac[:2])
-    finally:
-        del os.environ["BSI_FORCE_CONFIG"]
+    n = plan.config()[1]
+    for bad in (str(n), "-1", "7x"):
+        os.environ["BSI_FORCE_CONFIG"] = bad
+        try:
+            with pytest.raises(bsi.BSIError):
+                plan.tune()
+            with pytest.raises(bsi.BSIError):
+                bsi.BatchPlan(dims[:2], spac[:2])
+        finally:
+            del os.environ["BSI_FORCE_CONFIG"]
     plan.close()

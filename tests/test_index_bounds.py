@@ -60,3 +60,13 @@ def test_batched_workload_volumes(check):
     for d, s in zip(dims, spac):
         rc, msg = check(tuple(int(v) for v in d), tuple(int(v) for v in s))
         assert rc == 0, (tuple(d), tuple(s), msg)
+
+
+def test_batched_item_loops_end_and_cover():
+    """The batched kernels' item loops: each item once, every loop ends (a grid
+    of one workgroup per item takes exactly its own item)."""
+    L = ctypes.CDLL(LIB)
+    L.bsi_check_batch_items.argtypes = [ctypes.c_char_p, ctypes.c_int]
+    L.bsi_check_batch_items.restype = ctypes.c_int
+    msg = ctypes.create_string_buffer(512)
+    assert L.bsi_check_batch_items(msg, 512) == 0, msg.value.decode()
