@@ -160,6 +160,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--quick", action="store_true", help="main step only: no extras, no CPU baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline")
+    ap.add_argument("--with-registration", action="store_true",
+                    help="with --quick: also time the registration iteration, fused and unfused")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run 3 plain device-to-device copies of 805,306,368 bytes (the known-size "
                          "reference that rocprofv3 FETCH_SIZE / WRITE_SIZE are scaled by)")
@@ -268,6 +270,8 @@ def main():
     extras = {}
     if not args.quick:
         extras = run_extras(torch, bsi, workloads)
+    elif args.with_registration:
+        extras = registration_iterations(torch, bsi, workloads)
     cpu = None
     if not args.quick and not args.no_cpu and rank == 0:
         log("cpu baseline (oracle)")
@@ -411,7 +415,14 @@ def run_extras(torch, bsi, workloads):
     log("scalar upsampling:", ex["scalar_upsample_512x512x256_x4"])
     del coarse, image
 
-    # one SSD registration iteration at 256 x 256 x 160 (moving image made on the GPU)
+    ex.update(registration_iterations(torch, bsi, workloads))
+    return ex
+
+
+def registration_iterations(torch, bsi, workloads):
+    """One SSD registration iteration at 256 x 256 x 160, fused and unfused
+    (the moving image is made on the GPU)."""
+    ex = {}
     c = workloads.cfg4()
     dims, sp = c["dims"], c["spacing"]
     fixed = torch.from_numpy(c["fixed"]).cuda()
