@@ -229,9 +229,10 @@ int32_t bsi_ssd_fused_workspace_size(const int32_t dims[3], const int32_t spacin
      loss[0]   = sum_x r^2 (FP32, fixed order),
      grid_grad = B^T [2 r dW/dp]  (the adjoint of Eq. 1 applied to the
                  bsi_ssd_grad field gradient), OVERWRITTEN.
-   The result equals bsi_forward -> bsi_ssd_grad -> bsi_adjoint up to FP32
-   rounding: T is summed in another order, so a sample coordinate within
-   rounding of a cell boundary can fall in the neighbouring cell.
+   grid_grad equals bsi_forward -> bsi_ssd_grad -> bsi_adjoint bit for bit
+   (T is formed with the forward's operations, the residual and gradient with
+   the SSD kernel's, and the adjoint is the same pass 1 and pass 2); the loss
+   is summed in another fixed order than bsi_ssd_grad's.
    grid: [gz][gy][gx][3]; moving, fixed: [nz][ny][nx]; grid_grad as grid;
    loss: one device float.  workspace: device scratch of at least
    bsi_ssd_fused_workspace_size() bytes, owned by the caller, not shared by
@@ -241,6 +242,18 @@ int32_t bsi_ssd_fused(const float* grid, const float* moving, const float* fixed
                       const int32_t dims[3], const int32_t spacing[3], float* grid_grad,
                       float* loss, void* workspace, size_t workspace_bytes,
                       hipStream_t stream);
+
+/* One fused registration iteration: bsi_ssd_fused at the current grid, then
+   grid -= eta * grid_grad (each float as bsi_descent_step computes it), with
+   the descent update and the loss sum folded into the gradient's launch.
+   grid is read and updated in place; the other arguments are those of
+   bsi_ssd_fused (same workspace size).  grid_grad and loss hold the gradient
+   and loss at the grid before the update.  Errors: INVALID_ARG (also a
+   non-finite eta), UNSUPPORTED, NO_DEVICE, HIP. */
+int32_t bsi_ssd_fused_descent(float* grid, const float* moving, const float* fixed,
+                              const int32_t dims[3], const int32_t spacing[3], float eta,
+                              float* grid_grad, float* loss, void* workspace,
+                              size_t workspace_bytes, hipStream_t stream);
 
 /* Gradient-descent update grid[i] -= eta * grad[i] for i < count (count = number
    of floats).  Errors: INVALID_ARG, NO_DEVICE, HIP. */

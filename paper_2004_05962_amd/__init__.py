@@ -13,7 +13,7 @@ from ._lib import (BSIError, bsi_adjoint, bsi_adjoint_noalloc, bsi_adjoint_gener
                    bsi_batch_launch, bsi_batch_run, bsi_batch_run_separate, bsi_batch_tune,
                    bsi_descent_step, bsi_forward, bsi_forward_general, bsi_forward_lerp,
                    bsi_forward_scalar, bsi_general_grid_dims, bsi_grid_dims, bsi_last_error, bsi_ssd_fused,
-                   bsi_ssd_fused_workspace_size, bsi_ssd_grad, bsi_ssd_workspace_size, bsi_version,
+                   bsi_ssd_fused_descent, bsi_ssd_fused_workspace_size, bsi_ssd_grad, bsi_ssd_workspace_size, bsi_version,
                    bsi_warp, field_shape, general_grid_shape, grid_shape, upsample)
 from .autograd import BSIFunction, adjoint, bsi, forward
 from .batch import BatchPlan

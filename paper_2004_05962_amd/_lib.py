@@ -29,7 +29,7 @@ EXPORTS = (
     "bsi_adjoint_workspace_size",
     "bsi_adjoint", "bsi_adjoint_partials", "bsi_adjoint_reduce", "bsi_adjoint_noalloc", "bsi_general_grid_dims",
     "bsi_forward_general", "bsi_adjoint_general_workspace_size", "bsi_adjoint_general", "bsi_warp", "bsi_ssd_workspace_size", "bsi_ssd_grad", "bsi_ssd_fused_workspace_size", "bsi_ssd_fused",
-    "bsi_descent_step",
+    "bsi_ssd_fused_descent", "bsi_descent_step",
     "bsi_batch_create", "bsi_batch_bind", "bsi_batch_tune", "bsi_batch_config", "bsi_batch_describe", "bsi_batch_run",
     "bsi_batch_run_separate", "bsi_batch_capture", "bsi_batch_launch", "bsi_batch_destroy",
 )
@@ -78,6 +78,7 @@ def lib():
         "bsi_ssd_grad": ([_VP, _VP, _VP, p3, _VP, _VP, _VP, sz, _VP], i32),
         "bsi_ssd_fused_workspace_size": ([p3, p3, ctypes.POINTER(sz)], i32),
         "bsi_ssd_fused": ([_VP, _VP, _VP, p3, p3, _VP, _VP, _VP, sz, _VP], i32),
+        "bsi_ssd_fused_descent": ([_VP, _VP, _VP, p3, p3, ctypes.c_float, _VP, _VP, _VP, sz, _VP], i32),
         "bsi_descent_step": ([_VP, _VP, ctypes.c_float, i64, _VP], i32),
         "bsi_batch_create": ([i32, p3, p3, ctypes.POINTER(_VP)], i32),
         "bsi_batch_bind": ([_VP, ctypes.POINTER(_VP), ctypes.POINTER(_VP), ctypes.POINTER(_VP),
@@ -345,6 +346,19 @@ def bsi_ssd_fused(grid, moving, fixed, dims, spacing, grid_grad, loss, workspace
     w, nbytes = _workspace(workspace)
     _check(lib().bsi_ssd_fused(g, m, x, _triple(dims, "dims"), _triple(spacing, "spacing"), o, l, w, nbytes,
                                _stream(stream)))
+
+
+def bsi_ssd_fused_descent(grid, moving, fixed, dims, spacing, eta, grid_grad, loss, workspace, stream=None):
+    """One fused registration iteration: loss and gradient at `grid`, then grid -= eta * grad in place."""
+    nx, ny, nz = (int(v) for v in dims)
+    g = _ptr(grid, "grid", grid_shape(dims, spacing))
+    m = _ptr(moving, "moving", (nz, ny, nx))
+    x = _ptr(fixed, "fixed", (nz, ny, nx))
+    o = _ptr(grid_grad, "grid_grad", grid_shape(dims, spacing))
+    l = _ptr(loss, "loss", (1,))
+    w, nbytes = _workspace(workspace)
+    _check(lib().bsi_ssd_fused_descent(g, m, x, _triple(dims, "dims"), _triple(spacing, "spacing"),
+                                       ctypes.c_float(float(eta)), o, l, w, nbytes, _stream(stream)))
 
 
 def bsi_descent_step(grid, grad, eta, stream=None):

@@ -4,6 +4,7 @@
 
 #include <cstdio>
 #include <limits>
+#include <cmath>
 #include <string>
 
 #include "bsi.h"
@@ -405,6 +406,35 @@ int32_t bsi_ssd_fused(const float* grid, const float* moving, const float* fixed
   if ((rc = device_lut(&lut))) return rc;
   hipError_t e = launch_ssd_fused(grid, moving, fixed, grid_grad, loss, a, lut, workspace, stream);
   return e == hipSuccess ? BSI_OK : hip_fail(e, "launching the fused SSD kernels");
+}
+
+int32_t bsi_ssd_fused_descent(float* grid, const float* moving, const float* fixed, const int32_t dims[3],
+                              const int32_t spacing[3], float eta, float* grid_grad, float* loss, void* workspace,
+                              size_t workspace_bytes, hipStream_t stream) {
+  clear_error();
+  VolGeom g;
+  int32_t rc = make_geom(dims, spacing, &g);
+  if (rc) return rc;
+  if (!grid) return null_arg("grid");
+  if (!moving) return null_arg("moving");
+  if (!fixed) return null_arg("fixed");
+  if (!grid_grad) return null_arg("grid_grad");
+  if (!loss) return null_arg("loss");
+  if (!workspace) return null_arg("workspace");
+  if (!std::isfinite(eta)) {
+    set_error("eta must be finite");
+    return BSI_ERR_INVALID_ARG;
+  }
+  const AdjGeom a = make_adj_geom(g);
+  const size_t need = fused_workspace_bytes(a);
+  if (workspace_bytes < need) {
+    set_error("workspace too small: need " + std::to_string(need) + " bytes");
+    return BSI_ERR_INVALID_ARG;
+  }
+  const float* lut = nullptr;
+  if ((rc = device_lut(&lut))) return rc;
+  hipError_t e = launch_ssd_fused(grid, moving, fixed, grid_grad, loss, a, lut, workspace, stream, grid, eta);
+  return e == hipSuccess ? BSI_OK : hip_fail(e, "launching the fused SSD step");
 }
 
 int32_t bsi_descent_step(float* grid, const float* grad, float eta, int64_t count, hipStream_t stream) {

@@ -64,8 +64,11 @@ hipError_t launch_ssd_grad(const float* field, const float* moving, const float*
 hipError_t launch_sum(const float* partials, long n, float* out, hipStream_t s);
 // Fused BSI -> warp -> SSD -> adjoint (fused.hip).
 size_t fused_workspace_bytes(const AdjGeom& a);
+// descend_grid: null, or the grid to update in place by grid -= eta * grad
+// after the gradient is formed (the descent step folded into the last launch).
 hipError_t launch_ssd_fused(const float* grid, const float* moving, const float* fixed, float* grad, float* loss,
-                            const AdjGeom& a, const float* lut, void* workspace, hipStream_t s);
+                            const AdjGeom& a, const float* lut, void* workspace, hipStream_t s,
+                            float* descend_grid = nullptr, float eta = 0.f);
 // Real spacing s and origin o per axis (general.hip): control point a at voxel
 // o + (a - 1) s, n voxels, g control points.
 struct GenAxis {

@@ -300,8 +300,46 @@ size_t fused_workspace_bytes(const AdjGeom& a) {
   return p + (size_t)a.x.nb * a.y.nb * a.z.nb * sizeof(float);
 }
 
+// The fused step's tail in one launch: workgroups [0, nblk) are pass 2 (the
+// fixed-order gather of each control point's partials), and with `descend`
+// also the descent update grid -= eta grad of the points they gather (pass 1
+// has finished reading the grid: it ran before, on the same stream); workgroup
+// nblk sums the bricks' loss partials in a fixed order.
+constexpr int kTailThreads = kGatherThreads;
+
+__global__ __launch_bounds__(kTailThreads) void fused_tail_kernel(const float* __restrict__ part,
+                                                                   float* __restrict__ grad, float* __restrict__ grid,
+                                                                   float eta, int descend,
+                                                                   const float* __restrict__ lpart, int nlp,
+                                                                   float* __restrict__ loss, AdjGeom a, int nblk) {
+  if ((int)blockIdx.x == nblk) {
+    __shared__ float red[kTailThreads];
+    float acc = 0.f;
+    for (int i = threadIdx.x; i < nlp; i += kTailThreads) acc += lpart[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = kTailThreads / 2; h > 0; h >>= 1) {
+      if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = red[0];
+    return;
+  }
+  int cx, cy, cz;
+  if (!adj_gather_index(a.g, blockIdx.x, uniform(threadIdx.x / kWave), threadIdx.x & (kWave - 1), cx, cy, cz))
+    return;
+  const size_t i = ((size_t)cz * a.g.gy + cy) * a.g.gx + cx;
+  const F3 gv = adj_gather_point(part, a, cx, cy, cz);
+  stf3(grad + i * 3, gv);
+  if (descend) {  // the descent kernel's update, on the same values
+    float* p = grid + i * 3;
+    stf3(p, F3{fmaf(-eta, gv.x, p[0]), fmaf(-eta, gv.y, p[1]), fmaf(-eta, gv.z, p[2])});
+  }
+}
+
 hipError_t launch_ssd_fused(const float* grid, const float* moving, const float* fixed, float* grad, float* loss,
-                            const AdjGeom& a, const float* lut, void* workspace, hipStream_t s) {
+                            const AdjGeom& a, const float* lut, void* workspace, hipStream_t s, float* descend_grid,
+                            float eta) {
   float* part = static_cast<float*>(workspace);
   float* lpart = reinterpret_cast<float*>(static_cast<char*>(workspace) +
                                           (adj_workspace_bytes(a) + 255) / 256 * 256);
@@ -330,8 +368,12 @@ hipError_t launch_ssd_fused(const float* grid, const float* moving, const float*
 #undef BSI_FUSED_CASE
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if ((e = launch_adjoint_reduce(part, grad, a, s)) != hipSuccess) return e;
-  return launch_sum(lpart, nbricks, loss, s);
+  const int64_t nblk = adj_gather_blocks(a.g);
+  if (nblk + 1 >= ((int64_t)1 << 31) || nbricks >= ((int64_t)1 << 31))
+    return hipErrorInvalidConfiguration;  // a field far beyond device memory
+  hipLaunchKernelGGL(fused_tail_kernel, dim3((unsigned)(nblk + 1)), dim3(kTailThreads), 0, s, part, grad, descend_grid,
+                     eta, descend_grid != nullptr ? 1 : 0, lpart, (int)nbricks, loss, a, (int)nblk);
+  return hipGetLastError();
 }
 
 }  // namespace bsi

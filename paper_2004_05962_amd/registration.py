@@ -6,9 +6,11 @@ similarity standing in for the paper's NiftyReg measure):
   loss, dL/dfield                       bsi_ssd_grad
   g = B^T dL/dfield                     bsi_adjoint
   grid -= eta * g                       bsi_descent_step
-With ``fused=True`` (the default) the first three are one call, bsi_ssd_fused,
+With ``fused=True`` (the default) an iteration is one call, bsi_ssd_fused_descent,
 which never stores the field or dL/dfield (the merge of FFD steps into BSI that
-Sec. 8 names as further work); the results agree up to FP32 rounding.
+Sec. 8 names as further work) and folds the update into its last launch; the
+gradient and the updated grid equal the unfused ones bit for bit, the loss is
+summed in another fixed order.
 All calls run on one stream; losses are written into a device buffer, so the host
 synchronises only when it reads them.  ``losses[s]`` is the loss of grid_s,
 before its update.  State for checkpoint/resume is (grid, step, eta).
@@ -16,7 +18,7 @@ before its update.  State for checkpoint/resume is (grid, step, eta).
 import torch
 
 from ._lib import (bsi_adjoint, bsi_adjoint_workspace_size, bsi_descent_step, bsi_forward, bsi_ssd_fused,
-                   bsi_ssd_fused_workspace_size, bsi_ssd_grad, bsi_ssd_workspace_size, field_shape, grid_shape)
+                   bsi_ssd_fused_descent, bsi_ssd_fused_workspace_size, bsi_ssd_grad, bsi_ssd_workspace_size, field_shape, grid_shape)
 
 
 class SSDRegistration:
@@ -72,8 +74,12 @@ class SSDRegistration:
             raise ValueError("set eta (or call auto_eta) before stepping")
         if self.step_index >= self.losses.numel():
             raise RuntimeError("loss buffer full")
-        self.evaluate(stream=stream)
-        bsi_descent_step(self.grid, self.grad, self.eta, stream)
+        if self.fused:  # evaluation and update in one call (the update folded into its last launch)
+            bsi_ssd_fused_descent(self.grid, self.moving, self.fixed, self.dims, self.spacing, self.eta, self.grad,
+                                  self.losses[self.step_index:self.step_index + 1], self.ws_fused, stream)
+        else:
+            self.evaluate(stream=stream)
+            bsi_descent_step(self.grid, self.grad, self.eta, stream)
         self.step_index += 1
 
     def run(self, steps, stream=None):

@@ -96,6 +96,12 @@ def test_null_pointers_rejected_before_device():
         args = [P, P, P, d, s, P, P, P, 1 << 30, NULL]
         args[[0, 1, 2, 5, 6, 7][k]] = NULL
         assert _call("bsi_ssd_fused", *args) == _lib.BSI_ERR_INVALID_ARG
+    for k in range(6):
+        args = [P, P, P, d, s, ctypes.c_float(0.5), P, P, P, 1 << 30, NULL]
+        args[[0, 1, 2, 6, 7, 8][k]] = NULL
+        assert _call("bsi_ssd_fused_descent", *args) == _lib.BSI_ERR_INVALID_ARG
+    assert _call("bsi_ssd_fused_descent", P, P, P, d, s, ctypes.c_float(float("inf")), P, P, P, 1 << 30,
+                 NULL) == _lib.BSI_ERR_INVALID_ARG
     assert _call("bsi_descent_step", NULL, P, ctypes.c_float(1.0), 4, NULL) == _lib.BSI_ERR_INVALID_ARG
     assert _call("bsi_descent_step", P, P, ctypes.c_float(1.0), -1, NULL) == _lib.BSI_ERR_INVALID_ARG
     assert "non-null" in bsi.bsi_last_error() or "count" in bsi.bsi_last_error()
@@ -112,6 +118,8 @@ def test_workspace_size_checked_before_device():
     fused = bsi.bsi_ssd_fused_workspace_size((40, 30, 20), (5, 5, 5))
     assert fused > 0
     assert _call("bsi_ssd_fused", P, P, P, d, s, P, P, P, fused - 1, NULL) == _lib.BSI_ERR_INVALID_ARG
+    assert _call("bsi_ssd_fused_descent", P, P, P, d, s, ctypes.c_float(0.5), P, P, P, fused - 1,
+                 NULL) == _lib.BSI_ERR_INVALID_ARG
     ssd = bsi.bsi_ssd_workspace_size((40, 30, 20))
     assert _call("bsi_ssd_grad", P, P, P, d, P, P, P, ssd - 1, NULL) == _lib.BSI_ERR_INVALID_ARG
 

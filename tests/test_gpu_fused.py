@@ -125,3 +125,30 @@ def test_fused_rerun_bits_and_workspace_check():
     small = torch.empty(need - 4, dtype=torch.uint8, device="cuda")
     with pytest.raises(bsi.BSIError):
         bsi.bsi_ssd_fused(grid, M, X, dims, spacing, outs[0][0], outs[0][1], small)
+
+
+@pytest.mark.parametrize("dims,spacing", [((77, 45, 31), (5, 4, 6)), ((130, 40, 21), (5, 5, 5))])
+def test_fused_descent_equals_fused_then_descent(dims, spacing):
+    """bsi_ssd_fused_descent: gradient and loss at the grid as bsi_ssd_fused gives
+    them, and the grid updated exactly as bsi_descent_step updates it."""
+    say("fused descent", dims, spacing)
+    fixed, moving = _images(dims, seed=9)
+    grid0 = dev(workloads.random_grid(dims, spacing, 1.5, seed=4))
+    M, X = dev(moving), dev(fixed)
+    ws = torch.empty(bsi.bsi_ssd_fused_workspace_size(dims, spacing), dtype=torch.uint8, device="cuda")
+    eta = 0.37
+    ref_g = torch.empty(bsi.grid_shape(dims, spacing), device="cuda")
+    ref_l = torch.empty(1, device="cuda")
+    bsi.bsi_ssd_fused(grid0, M, X, dims, spacing, ref_g, ref_l, ws)
+    ref_grid = grid0.clone()
+    bsi.bsi_descent_step(ref_grid, ref_g, eta)
+    grid = grid0.clone()
+    g = torch.empty_like(ref_g)
+    loss = torch.empty(1, device="cuda")
+    bsi.bsi_ssd_fused_descent(grid, M, X, dims, spacing, eta, g, loss, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(g, ref_g)
+    assert torch.equal(loss, ref_l)
+    assert torch.equal(grid, ref_grid)
+    with pytest.raises(bsi.BSIError):
+        bsi.bsi_ssd_fused_descent(grid, M, X, dims, spacing, float("nan"), g, loss, ws)
