@@ -120,7 +120,8 @@ __device__ __forceinline__ F3 fused_contract(const float* __restrict__ slot, int
   return F3{q[0], q[1], q[2]};
 }
 
-template <int DX, bool StageAll>
+// Pairs: the sampler's x-neighbour loads (trilinear_load): 1 for nx >= 2, 0 for nx == 1.
+template <int DX, bool StageAll, int Pairs>
 __device__ __forceinline__ void fused_brick(const float* __restrict__ grid, const float* __restrict__ moving,
                                             const float* __restrict__ fixed, float* __restrict__ part,
                                             float* __restrict__ lpart, const AdjGeom& a,
@@ -204,39 +205,77 @@ __device__ __forceinline__ void fused_brick(const float* __restrict__ grid, cons
     }
   };
 
+  // Per voxel plane, in two stages: (a) T from the 4 contracted planes, the
+  // sample's cell and the loads of its corners and of `fixed`; (b) the
+  // residual, the gradient and the z-accumulation.  Within a z-tile, (a) of
+  // the next plane is issued before (b) of the current one, so a wave keeps
+  // one plane's loads in flight while it finishes the previous plane.  Every
+  // lane loads (a lane outside the brick from its clamped column and row, and
+  // a clamped sample position), so that no load is conditional and waiting
+  // for one plane's loads leaves the next plane's in flight; (b) ignores the
+  // values of such lanes.
+  static_assert(R == 1, "one voxel row per lane");
+  struct Pending {
+    SampleIn s;
+    float fx;
+    float w[4];  // Bz_0..3 of the plane's offset in its tile
+  };
   const size_t izs = (size_t)g.ny * g.nx;
-  int oz = 0;
-  for (int z = b.z0; z < b.ze; ++z) {
+  const int y = yv[0];
+  const size_t fxy = (size_t)imin(y, b.ye - 1) * g.nx + xc;  // the lane's (clamped) voxel column
+  auto stage_a = [&](int z, int oz) {
+    Pending p;
     const float* wz = lut_row(lut, g.dz, oz);
-    const float w0 = wz[0], w1 = wz[1], w2 = wz[2], w3 = wz[3];
-    float fx[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) fx[r] = act[r] ? fixed[(size_t)z * izs + (size_t)yv[r] * g.nx + x] : 0.f;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      // T as the forward kernel forms it
-      const F3 t{fmaf(w3, Q[r][3].x, fmaf(w2, Q[r][2].x, fmaf(w1, Q[r][1].x, w0 * Q[r][0].x))),
-                 fmaf(w3, Q[r][3].y, fmaf(w2, Q[r][2].y, fmaf(w1, Q[r][1].y, w0 * Q[r][0].y))),
-                 fmaf(w3, Q[r][3].z, fmaf(w2, Q[r][2].z, fmaf(w1, Q[r][1].z, w0 * Q[r][0].z)))};
-      F3 d{0.f, 0.f, 0.f};
-      if (act[r]) {
-        // the SSD kernel's sample and gradient
-        const Sample s = trilinear(moving, g.nx, g.ny, g.nz, (float)x + t.x, (float)yv[r] + t.y, (float)z + t.z);
-        const float res = s.w - fx[r];
-        l2 = fmaf(res, res, l2);
-        const float two_r = 2.f * res;
-        d = F3{two_r * s.gx, two_r * s.gy, two_r * s.gz};
-      }
-      // the adjoint's z-accumulation
-      const float ws[4] = {w0, w1, w2, w3};
-#pragma unroll
-      for (int n = 0; n < 4; ++n) {
-        acc[r][n].x = fmaf(ws[n], d.x, acc[r][n].x);
-        acc[r][n].y = fmaf(ws[n], d.y, acc[r][n].y);
-        acc[r][n].z = fmaf(ws[n], d.z, acc[r][n].z);
-      }
+    for (int n = 0; n < 4; ++n) p.w[n] = wz[n];
+    p.fx = fixed[(size_t)z * izs + fxy];
+    // T as the forward kernel forms it
+    const F3 t{fmaf(p.w[3], Q[0][3].x, fmaf(p.w[2], Q[0][2].x, fmaf(p.w[1], Q[0][1].x, p.w[0] * Q[0][0].x))),
+               fmaf(p.w[3], Q[0][3].y, fmaf(p.w[2], Q[0][2].y, fmaf(p.w[1], Q[0][1].y, p.w[0] * Q[0][0].y))),
+               fmaf(p.w[3], Q[0][3].z, fmaf(p.w[2], Q[0][2].z, fmaf(p.w[1], Q[0][1].z, p.w[0] * Q[0][0].z)))};
+    p.s = trilinear_load<Pairs>(moving, g.nx, g.ny, g.nz, (float)x + t.x, (float)y + t.y, (float)z + t.z);
+    return p;
+  };
+  auto stage_b = [&](const Pending& p) {
+    F3 d{0.f, 0.f, 0.f};
+    if (act[0]) {
+      // the SSD kernel's residual and gradient
+      const Sample s = trilinear_finish(p.s);
+      const float res = s.w - p.fx;
+      l2 = fmaf(res, res, l2);
+      const float two_r = 2.f * res;
+      d = F3{two_r * s.gx, two_r * s.gy, two_r * s.gz};
     }
-    if (++oz == g.dz && z + 1 < b.ze) {
+    // the adjoint's z-accumulation
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      acc[0][n].x = fmaf(p.w[n], d.x, acc[0][n].x);
+      acc[0][n].y = fmaf(p.w[n], d.y, acc[0][n].y);
+      acc[0][n].z = fmaf(p.w[n], d.z, acc[0][n].z);
+    }
+  };
+
+  for (int z = b.z0; z < b.ze;) {  // one z-tile (the brick's last may be partial)
+    const int np = imin(g.dz, b.ze - z);
+    // two register sets, used in turn (a copy from one to the other would
+    // wait for the loads it copies)
+    Pending p0 = stage_a(z, 0);
+    int k = 0;
+    for (; k + 2 < np; k += 2) {
+      const Pending p1 = stage_a(z + k + 1, k + 1);
+      stage_b(p0);
+      p0 = stage_a(z + k + 2, k + 2);
+      stage_b(p1);
+    }
+    if (k + 1 < np) {
+      const Pending p1 = stage_a(z + k + 1, k + 1);
+      stage_b(p0);
+      stage_b(p1);
+    } else {
+      stage_b(p0);
+    }
+    z += np;
+    if (np == g.dz && z < b.ze) {
       // plane tz + 4 goes to the slot of plane tz + 2, contracted before the
       // previous tile's barrier; the emission's barrier orders the store
       // before the contraction below
@@ -258,7 +297,6 @@ __device__ __forceinline__ void fused_brick(const float* __restrict__ grid, cons
         Q[r][3] = fused_contract<DX>(sm.ring[(tz + 4) & 1], base[r], bx, by[r]);
       }
       ++tz;
-      oz = 0;
       more = (tz + 1) * g.dz < b.ze;
       if (more) fused_fetch<DX>(grid, g, map, tz + 4, st);
     }
@@ -276,7 +314,7 @@ __device__ __forceinline__ void fused_brick(const float* __restrict__ grid, cons
   if (tid == 0) lpart[brick] = sm.red[0];
 }
 
-template <int DX>
+template <int DX, int Pairs = 1>
 __global__ __launch_bounds__(kFusedThreads) void fused_pass1_kernel(const float* __restrict__ grid,
                                                                   const float* __restrict__ moving,
                                                                   const float* __restrict__ fixed,
@@ -288,9 +326,9 @@ __global__ __launch_bounds__(kFusedThreads) void fused_pass1_kernel(const float*
   const int brick = xcd_remap(blockIdx.x, gridDim.x);
   if (brick >= nbricks) return;  // uniform over the workgroup
   if (adj_stage_all(a))
-    fused_brick<DX, true>(grid, moving, fixed, part, lpart, a, lut, brick, sm, threadIdx.x);
+    fused_brick<DX, true, Pairs>(grid, moving, fixed, part, lpart, a, lut, brick, sm, threadIdx.x);
   else
-    fused_brick<DX, false>(grid, moving, fixed, part, lpart, a, lut, brick, sm, threadIdx.x);
+    fused_brick<DX, false, Pairs>(grid, moving, fixed, part, lpart, a, lut, brick, sm, threadIdx.x);
 }
 
 }  // namespace
@@ -350,7 +388,11 @@ hipError_t launch_ssd_fused(const float* grid, const float* moving, const float*
     hipLaunchKernelGGL(fused_pass1_kernel<D>, gridd, block, 0, s, grid, moving, fixed, part, lpart, a, lut); \
     break;
   static_assert(kAdjMaxDX == 12, "one case per specialised spacing");
-  switch (a.g.dx) {
+  // a volume one voxel wide samples its x-neighbours one by one (generic kernel)
+  switch (a.g.nx >= 2 ? a.g.dx : -1) {
+    case -1:
+      hipLaunchKernelGGL((fused_pass1_kernel<0, 0>), gridd, block, 0, s, grid, moving, fixed, part, lpart, a, lut);
+      break;
     BSI_FUSED_CASE(1)
     BSI_FUSED_CASE(2)
     BSI_FUSED_CASE(3)

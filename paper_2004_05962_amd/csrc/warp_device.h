@@ -41,41 +41,64 @@ struct Sample {
   float gx, gy, gz;   // dW/dp, masked at the border
 };
 
-__device__ __forceinline__ Sample trilinear(const float* __restrict__ img, int nx, int ny, int nz,
-                                            float px, float py, float pz) {
+// The sample in two halves, so that a caller can issue the loads of one
+// sample before it finishes the previous one: trilinear_load forms the cell
+// and loads its 8 corners, trilinear_finish interpolates.
+struct SampleIn {
+  float c000, c001, c010, c011, c100, c101, c110, c111;  // corners, x fastest
+  float fx, fy, fz;                                      // offsets in the cell
+  float inx, iny, inz;                                   // 1 strictly inside, else 0
+};
+
+// Pairs: 1 when the caller guarantees nx >= 2 (x-neighbours as one 8-byte
+// load, no branch), 0 when nx == 1, -1 to test nx here.
+template <int Pairs = -1>
+__device__ __forceinline__ SampleIn trilinear_load(const float* __restrict__ img, int nx, int ny, int nz, float px,
+                                                   float py, float pz) {
   const Axis ax = sample_axis(px, nx), ay = sample_axis(py, ny), az = sample_axis(pz, nz);
   const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
   const float* p00 = img + az.i0 * sz + ay.i0 * sy;
   const float* p01 = img + az.i0 * sz + ay.i1 * sy;
   const float* p10 = img + az.i1 * sz + ay.i0 * sy;
   const float* p11 = img + az.i1 * sz + ay.i1 * sy;
-  float c000, c001, c010, c011, c100, c101, c110, c111;
-  if (nx >= 2) {
+  SampleIn s;
+  if (Pairs == 1 || (Pairs == -1 && nx >= 2)) {
     // i1 = i0 + 1: each pair of x-neighbours is one 8-byte load
     const F2 q00 = ldf2(p00 + ax.i0), q01 = ldf2(p01 + ax.i0);
     const F2 q10 = ldf2(p10 + ax.i0), q11 = ldf2(p11 + ax.i0);
-    c000 = q00.x, c001 = q00.y, c010 = q01.x, c011 = q01.y;
-    c100 = q10.x, c101 = q10.y, c110 = q11.x, c111 = q11.y;
+    s.c000 = q00.x, s.c001 = q00.y, s.c010 = q01.x, s.c011 = q01.y;
+    s.c100 = q10.x, s.c101 = q10.y, s.c110 = q11.x, s.c111 = q11.y;
   } else {
-    c000 = c001 = p00[0];
-    c010 = c011 = p01[0];
-    c100 = c101 = p10[0];
-    c110 = c111 = p11[0];
+    s.c000 = s.c001 = p00[0];
+    s.c010 = s.c011 = p01[0];
+    s.c100 = s.c101 = p10[0];
+    s.c110 = s.c111 = p11[0];
   }
-  const float fx = ax.f, fy = ay.f, fz = az.f;
+  s.fx = ax.f, s.fy = ay.f, s.fz = az.f;
+  s.inx = ax.in, s.iny = ay.in, s.inz = az.in;
+  return s;
+}
+
+__device__ __forceinline__ Sample trilinear_finish(const SampleIn& c) {
+  const float fx = c.fx, fy = c.fy, fz = c.fz;
   // interpolate along x, then y, then z
-  const float x00 = fmaf(fx, c001 - c000, c000), x01 = fmaf(fx, c011 - c010, c010);
-  const float x10 = fmaf(fx, c101 - c100, c100), x11 = fmaf(fx, c111 - c110, c110);
+  const float x00 = fmaf(fx, c.c001 - c.c000, c.c000), x01 = fmaf(fx, c.c011 - c.c010, c.c010);
+  const float x10 = fmaf(fx, c.c101 - c.c100, c.c100), x11 = fmaf(fx, c.c111 - c.c110, c.c110);
   const float y0 = fmaf(fy, x01 - x00, x00), y1 = fmaf(fy, x11 - x10, x10);
   Sample s;
   s.w = fmaf(fz, y1 - y0, y0);
   // analytic derivatives of the trilinear form
-  const float dx00 = c001 - c000, dx01 = c011 - c010, dx10 = c101 - c100, dx11 = c111 - c110;
+  const float dx00 = c.c001 - c.c000, dx01 = c.c011 - c.c010, dx10 = c.c101 - c.c100, dx11 = c.c111 - c.c110;
   const float dx0 = fmaf(fy, dx01 - dx00, dx00), dx1 = fmaf(fy, dx11 - dx10, dx10);
-  s.gx = fmaf(fz, dx1 - dx0, dx0) * ax.in;
-  s.gy = fmaf(fz, (x11 - x10) - (x01 - x00), x01 - x00) * ay.in;
-  s.gz = (y1 - y0) * az.in;
+  s.gx = fmaf(fz, dx1 - dx0, dx0) * c.inx;
+  s.gy = fmaf(fz, (x11 - x10) - (x01 - x00), x01 - x00) * c.iny;
+  s.gz = (y1 - y0) * c.inz;
   return s;
+}
+
+__device__ __forceinline__ Sample trilinear(const float* __restrict__ img, int nx, int ny, int nz, float px, float py,
+                                            float pz) {
+  return trilinear_finish(trilinear_load(img, nx, ny, nz, px, py, pz));
 }
 
 }  // namespace bsi
