@@ -18,14 +18,16 @@
 // (by one, since s >= 1), with the next plane loaded while the current tile is
 // written and one barrier per tile.
 //
-// Adjoint: three separable gathers in a fixed order, one output per thread:
-//   A[z][y][cx]  = sum_x  Bx(x; cx)  dfield[z][y][x]       x ascending
-//   Bm[z][cy][cx] = sum_y By(y; cy)  A[z][y][cx]           y ascending
-//   grad[cz][cy][cx] = sum_z Bz(z; cz) Bm[z][cy][cx]        z ascending
-// where B(x; c) = B_{c - i(x)}(u(x)) for the voxels whose window holds c.  The
-// per-axis tables i(x), B(u(x)) are computed once per call into the workspace.
+// Adjoint: the per-axis tables i(x), B(u(x)) and the first voxel of every
+// tile are computed once per call into the workspace; then the aligned
+// adjoint's two passes, z-first, with the tables in place of equal tiles
+// (gen_zf_pass1_kernel: bricks of 64 x 16 voxels by whole z-tiles, the
+// z-contraction in registers, each finished control plane contracted over x
+// and y in LDS; gen_zf_pass2_kernel: the fixed-order sum of brick partials per
+// control point).  Deterministic, no atomics.
 #include <cmath>
 
+#include "adjoint_device.h"
 #include "bsi_internal.h"
 
 namespace bsi {
@@ -204,156 +206,342 @@ __global__ __launch_bounds__(kFwdThreads) void gen_fwd_kernel(const float* __res
   }
 }
 
-// Per-axis tables: tile[v] = i(v), w[v][0..3] = B(u(v)), for v < n.
-__global__ __launch_bounds__(256) void gen_table_kernel(GenAxis a, int* __restrict__ tile,
-                                                         float* __restrict__ w) {
-  const int v = blockIdx.x * 256 + threadIdx.x;
+// The three axes' tables in one launch: workgroups [0, nb[0]) take x, then y, then z.
+struct GenTables3 {
+  GenAxis ax[3];
+  int* tile[3];
+  float* w[3];
+  int* first[3];
+  int nb[3];  // workgroups per axis
+};
+
+__global__ __launch_bounds__(256) void gen_tables3_kernel(GenTables3 p) {
+  int blk = blockIdx.x, i = 0;
+  while (i < 2 && blk >= p.nb[i]) blk -= p.nb[i++];
+  const GenAxis a = p.ax[i];
+  const int v = blk * 256 + threadIdx.x;
   if (v >= a.n) return;
   float b[4];
-  tile[v] = gen_weights(a, v, b);
+  p.tile[i][v] = gen_weights(a, v, b);
 #pragma unroll
-  for (int l = 0; l < 4; ++l) w[4 * v + l] = b[l];
+  for (int l = 0; l < 4; ++l) p.w[i][4 * v + l] = b[l];
 }
 
-constexpr int kGatherChunk = 8;  // voxels loaded together per output
-
-// One separable gather along an axis.  The input is viewed as [outer][n][inner]
-// F3 values (n along the axis), the output as [outer][g][inner]; output
-// (o, c, k) sums the inputs (o, v, k) whose window holds c, v ascending.
-__global__ __launch_bounds__(256) void gen_gather_kernel(const float* __restrict__ in, float* __restrict__ out,
-                                                          GenAxis a, const int* __restrict__ tile,
-                                                          const int* __restrict__ first, const float* __restrict__ w,
-                                                          long outer, int inner) {
-  const long id = (long)blockIdx.x * 256 + threadIdx.x;
-  const long total = outer * a.g * (long)inner;
-  if (id >= total) return;
-  const int k = (int)(id % inner);
-  const long rest = id / inner;
-  const int c = (int)(rest % a.g);
-  const long o = rest / a.g;
-  // the voxels whose window holds c: c - 3 <= i(v) <= c, i.e. [first[c-3], first[c+1])
-  const int va = first[max(c - 3, 0)], vb = first[c + 1];
-  float sx = 0.f, sy = 0.f, sz = 0.f;
-  const float* src = in + ((size_t)o * a.n * inner + k) * 3;
-  // a chunk's loads are all issued before its sums (clamped indices, valid
-  // voxels summed in ascending order)
-  for (int v0 = va; v0 < vb; v0 += kGatherChunk) {
-    int vi[kGatherChunk];
-#pragma unroll
-    for (int j = 0; j < kGatherChunk; ++j) vi[j] = min(v0 + j, vb - 1);
-    float b[kGatherChunk];
-    F3 d[kGatherChunk];
-#pragma unroll
-    for (int j = 0; j < kGatherChunk; ++j) {
-      b[j] = w[4 * vi[j] + (c - tile[vi[j]])];
-      d[j] = ldf3(src + (size_t)vi[j] * inner * 3);
-    }
-#pragma unroll
-    for (int j = 0; j < kGatherChunk; ++j) {
-      if (v0 + j < vb) {
-        sx = fmaf(b[j], d[j].x, sx);
-        sy = fmaf(b[j], d[j].y, sy);
-        sz = fmaf(b[j], d[j].z, sz);
-      }
-    }
-  }
-  float* dst = out + (((size_t)o * a.g + c) * inner + k) * 3;
-  dst[0] = sx;
-  dst[1] = sy;
-  dst[2] = sz;
-}
-
-// First voxel of every tile of an axis: first[t] = min{v : i(v) >= t} for t = 0..g
-// (first[g] = n), from the nondecreasing table of window starts.
-__global__ __launch_bounds__(256) void gen_first_kernel(GenAxis a, const int* __restrict__ tile,
-                                                         int* __restrict__ first) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
+// First voxel of every tile of each axis (one launch for the three axes).
+__global__ __launch_bounds__(256) void gen_first3_kernel(GenTables3 p) {
+  int blk = blockIdx.x, i = 0;
+  while (i < 2 && blk >= p.nb[i]) blk -= p.nb[i++];
+  const GenAxis a = p.ax[i];
+  const int t = blk * 256 + threadIdx.x;
   if (t > a.g) return;
+  const int* tile = p.tile[i];
   int lo = 0, hi = a.n;
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
     if (tile[mid] < t) lo = mid + 1;
     else hi = mid;
   }
-  first[t] = lo;
+  p.first[i][t] = lo;
 }
 
-// The x pass of the adjoint by tile moments.  Along x, tile t is the run of
-// voxels [first[t], first[t+1]), and output c = sum_l M_l(c - l) (l ascending)
-// with M_l(t) = sum_{v in tile t} B_l(u(v)) d(v) (v ascending).  A wave takes
-// one row and kGxTiles consecutive tiles t0 .. t0+63 (t0 = c0 - 3): lane j
-// forms the moments of tile t0 + j from global memory (its tile's voxels are
-// contiguous, so the wave's loads cover a contiguous run), publishes them in
-// the wave's LDS region, and lanes j < kGxTiles - 3 then form output c0 + j.
-constexpr int kGxRows = 4;                 // rows per workgroup, one per wave
-constexpr int kGxThreads = kGxRows * kWave;
-constexpr int kGxTiles = kWave;            // tiles per wave
-constexpr int kGxOut = kGxTiles - 3;       // outputs per wave
-constexpr int kGxChunk = 6;                // voxels loaded together per lane
+// ---------------------------------------------------------------------------
+// The adjoint, z-first (as the aligned pass 1 in adjoint_device.h), with the
+// per-axis tables instead of tiles of equal length.  A brick is 64 x-voxels
+// (one per lane) by 16 rows (8 waves of 2 rows) by the voxels of kz whole
+// z-tiles, [first_z[b kz], first_z[(b+1) kz]).  Per voxel plane a lane adds
+// its 2 voxels into the 4 control planes they meet, with the plane's z
+// weights (scalar loads of the z table); slot k of the accumulators holds
+// control plane c with (c - cz0) mod 4 = k.  When the plane's z-tile ends,
+// control plane t is finished and is contracted in LDS: over x, output
+// column c of a row sums the brick's voxels v in [first_x[c-3], first_x[c+1])
+// (ascending) with weight B_{c - i(v)}(u(v)); then, after a workgroup barrier,
+// over y the same way, giving the brick's partial of that plane.  Pass 2
+// sums, per control point, the partials of the bricks meeting its support in
+// fixed order.  No atomics.
+constexpr int kGzBX = kWave;             // brick width (voxels)
+constexpr int kGzRows = 2;               // rows per lane
+constexpr int kGzWaves = 8;
+constexpr int kGzBY = kGzRows * kGzWaves;  // brick height (rows)
+constexpr int kGzThreads = kGzWaves * kWave;
+constexpr int kGzTargetZ = 48;           // about this many voxel planes per brick
+constexpr int kGzStage = 6144;           // floats of staged partials (24 KB)
 
-__global__ __launch_bounds__(kGxThreads) void gen_gather_x_kernel(const float* __restrict__ in,
-                                                                   float* __restrict__ out, GenAxis a,
-                                                                   const int* __restrict__ first,
-                                                                   const float* __restrict__ w, long rows) {
-  __shared__ float sm[kGxRows][kGxTiles * 12];
-  const int nseg = (a.g + kGxOut - 1) / kGxOut;
-  const long rblk = blockIdx.x / nseg;
-  const int seg = blockIdx.x - (int)(rblk * nseg);
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const long row = rblk * kGxRows + wave;
-  if (row >= rows) return;  // wave-uniform; no workgroup barrier below
-  const int c0 = seg * kGxOut;
-  const int t = c0 - 3 + lane;  // this lane's tile
-  float mm[12];
+struct GenAdj {
+  int nbx, nby, nbz;  // bricks per axis
+  int kz;             // z-tiles per brick
+  int cmx, cmy, cmz;  // window extents (the largest over the bricks)
+  int stage_all;      // the whole window of partials fits the LDS stage
+};
+
+// LDS of one workgroup (floats): F, H[2], the x and y tables, the stage.
+struct GzLayout {
+  int F, H, wx, tx, fx, wy, ty, fy, P, total;
+};
+__host__ __device__ inline GzLayout gz_layout(const GenAdj& a) {
+  GzLayout L;
+  int o = 0;
+  L.F = o;
+  o += kGzBY * kGzBX * 3;
+  L.H = o;
+  o += 2 * kGzBY * a.cmx * 3;
+  L.wx = o;
+  o += kGzBX * 4;
+  L.tx = o;
+  o += kGzBX;
+  L.fx = o;
+  o += a.cmx + 4;
+  L.wy = o;
+  o += kGzBY * 4;
+  L.ty = o;
+  o += kGzBY;
+  L.fy = o;
+  o += a.cmy + 4;
+  L.P = o;
+  o += a.stage_all ? a.cmz * a.cmy * a.cmx * 3 : 0;
+  L.total = o;
+  return L;
+}
+
+struct GzTables {
+  const int* tile[3];
+  const float* w[3];
+  const int* first[3];
+};
+
+// Brick (bx, by, bz): its voxel range and the first control index of its window per axis.
+struct GzBrick {
+  int x0, xe, y0, ye, z0, ze;
+  int cx0, cy0, cz0;
+  int Cx, Cy;
+};
+
+__device__ __forceinline__ GzBrick gz_brick(const GenGeom& q, const GenAdj& a, const GzTables& T, int id) {
+  GzBrick b;
+  const int bx = id % a.nbx;
+  const int r = id / a.nbx;
+  const int by = r % a.nby;
+  const int bz = r / a.nby;
+  b.x0 = bx * kGzBX;
+  b.xe = min(q.x.n, b.x0 + kGzBX);
+  b.y0 = by * kGzBY;
+  b.ye = min(q.y.n, b.y0 + kGzBY);
+  b.cz0 = bz * a.kz;
+  b.z0 = T.first[2][b.cz0];
+  b.ze = T.first[2][min(b.cz0 + a.kz, q.z.g - 3)];
+  b.cx0 = T.tile[0][b.x0];
+  b.Cx = T.tile[0][b.xe - 1] - b.cx0 + 4;
+  b.cy0 = T.tile[1][b.y0];
+  b.Cy = T.tile[1][b.ye - 1] - b.cy0 + 4;
+  return b;
+}
+
+__global__ __launch_bounds__(kGzThreads) void gen_zf_pass1_kernel(const float* __restrict__ dfield,
+                                                                   float* __restrict__ part, GenGeom q, GenAdj a,
+                                                                   GzTables T) {
+  extern __shared__ float gz_smem[];
+  const int nbricks = a.nbx * a.nby * a.nbz;
+  const int brick = xcd_remap(blockIdx.x, gridDim.x);
+  if (brick >= nbricks) return;  // uniform over the workgroup
+  const GzLayout L = gz_layout(a);
+  float* F = gz_smem + L.F;
+  float* wxT = gz_smem + L.wx;
+  int* txT = reinterpret_cast<int*>(gz_smem + L.tx);
+  int* fxT = reinterpret_cast<int*>(gz_smem + L.fx);
+  float* wyT = gz_smem + L.wy;
+  int* tyT = reinterpret_cast<int*>(gz_smem + L.ty);
+  int* fyT = reinterpret_cast<int*>(gz_smem + L.fy);
+  const GzBrick b = gz_brick(q, a, T, brick);
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = uniform(tid / kWave);
+  const int nxb = b.xe - b.x0, nyb = b.ye - b.y0;
+  // the brick's x and y tables; fxT[j] = first_x[cx0 + j - 3] (clamped at 0),
+  // so output column cx0 + j takes the voxels [fxT[j], fxT[j + 4])
+  if (tid < nxb) {
+    txT[tid] = T.tile[0][b.x0 + tid];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) mm[k] = 0.f;
-  if (t >= 0 && t < a.g - 3) {  // tiles 0 .. g-4 hold voxels
-    const float* src = in + (size_t)row * a.n * 3;
-    const int v1 = first[t + 1];
-    // a chunk's loads are all issued before its sums (clamped addresses, valid
-    // voxels summed in ascending order): several loads in flight per lane
-    for (int v0 = first[t]; v0 < v1; v0 += kGxChunk) {
-      F3 d[kGxChunk];
-      float b[kGxChunk][4];
+    for (int l = 0; l < 4; ++l) wxT[4 * tid + l] = T.w[0][4 * (b.x0 + tid) + l];
+  }
+  if (tid < nyb) {
+    tyT[tid] = T.tile[1][b.y0 + tid];
 #pragma unroll
-      for (int j = 0; j < kGxChunk; ++j) {
-        const int v = min(v0 + j, v1 - 1);
-        d[j] = ldf3(src + (size_t)v * 3);
+    for (int l = 0; l < 4; ++l) wyT[4 * tid + l] = T.w[1][4 * (b.y0 + tid) + l];
+  }
+  if (tid < b.Cx + 4) fxT[tid] = T.first[0][max(b.cx0 + tid - 3, 0)];
+  if (tid < b.Cy + 4) fyT[tid] = T.first[1][max(b.cy0 + tid - 3, 0)];
+  __syncthreads();
+
+  const size_t plane = (size_t)q.x.n * q.y.n * 3;
+  uint32_t off[kGzRows];
 #pragma unroll
-        for (int l = 0; l < 4; ++l) b[j][l] = w[4 * v + l];
-      }
+  for (int r = 0; r < kGzRows; ++r)
+    off[r] = ((uint32_t)min(b.y0 + wave * kGzRows + r, b.ye - 1) * (uint32_t)q.x.n +
+              (uint32_t)min(b.x0 + lane, b.xe - 1)) * 3u;
+  float* pbase = part + (size_t)brick * a.cmz * a.cmy * a.cmx * 3;
+  float* P = a.stage_all ? gz_smem + L.P : pbase;
+
+  F3 acc[4][kGzRows];
 #pragma unroll
-      for (int j = 0; j < kGxChunk; ++j) {
-        if (v0 + j < v1) {
+  for (int k = 0; k < 4; ++k)
 #pragma unroll
-          for (int l = 0; l < 4; ++l) {
-            mm[3 * l] = fmaf(b[j][l], d[j].x, mm[3 * l]);
-            mm[3 * l + 1] = fmaf(b[j][l], d[j].y, mm[3 * l + 1]);
-            mm[3 * l + 2] = fmaf(b[j][l], d[j].z, mm[3 * l + 2]);
-          }
+    for (int r = 0; r < kGzRows; ++r) acc[k][r] = F3{0.f, 0.f, 0.f};
+
+  // control plane CZL (slot PH, uniform): this wave's rows go to F, the slot is
+  // cleared, then the x- and y-contractions into the partials
+  auto contract = [&](int czl, bool last) {
+    float* H = gz_smem + L.H + (czl & 1) * kGzBY * a.cmx * 3;
+    // x: items (row of this wave, output column), each a run of the row's voxels
+    for (int it = lane; it < kGzRows * b.Cx; it += kWave) {
+      const int r = it / b.Cx, j = it - r * b.Cx;
+      const int row = wave * kGzRows + r;
+      if (row < nyb) {
+        const int c = b.cx0 + j;
+        const int va = max(fxT[j], b.x0) - b.x0, vb = min(fxT[j + 4], b.xe) - b.x0;
+        float sx = 0.f, sy = 0.f, sz = 0.f;
+        const float* Fr = F + row * kGzBX * 3;
+        for (int v = va; v < vb; ++v) {
+          const float wgt = wxT[4 * v + (c - txT[v])];
+          sx = fmaf(wgt, Fr[3 * v], sx);
+          sy = fmaf(wgt, Fr[3 * v + 1], sy);
+          sz = fmaf(wgt, Fr[3 * v + 2], sz);
         }
+        float* h = H + (row * a.cmx + j) * 3;
+        h[0] = sx;
+        h[1] = sy;
+        h[2] = sz;
       }
     }
-  }
-  float* mv = sm[wave];
-#pragma unroll
-  for (int k = 0; k < 12; ++k) mv[lane * 12 + k] = mm[k];
-  wave_lds_sync();
-  const int c = c0 + lane;
-  if (lane < kGxOut && c < a.g) {
-    float sx = 0.f, sy = 0.f, sz = 0.f;
-#pragma unroll
-    for (int l = 0; l < 4; ++l) {
-      const float* m = mv + (lane + 3 - l) * 12 + 3 * l;  // tile c - l (zero when it has no voxels)
-      sx += m[0];
-      sy += m[1];
-      sz += m[2];
+    __syncthreads();
+    // y: items (output row, output column) of the workgroup, each a run of rows
+    for (int it = tid; it < b.Cy * b.Cx; it += kGzThreads) {
+      const int i = it / b.Cx, j = it - i * b.Cx;
+      const int c = b.cy0 + i;
+      const int ya = max(fyT[i], b.y0) - b.y0, yb = min(fyT[i + 4], b.ye) - b.y0;
+      float sx = 0.f, sy = 0.f, sz = 0.f;
+      for (int y = ya; y < yb; ++y) {
+        const float wgt = wyT[4 * y + (c - tyT[y])];
+        const float* h = H + (y * a.cmx + j) * 3;
+        sx = fmaf(wgt, h[0], sx);
+        sy = fmaf(wgt, h[1], sy);
+        sz = fmaf(wgt, h[2], sz);
+      }
+      float* dst = P + ((size_t)(czl * a.cmy + i) * a.cmx + j) * 3;
+      dst[0] = sx;
+      dst[1] = sy;
+      dst[2] = sz;
     }
-    float* dst = out + ((size_t)row * a.g + c) * 3;
-    dst[0] = sx;
-    dst[1] = sy;
-    dst[2] = sz;
+    if (a.stage_all && last) {
+      __syncthreads();
+      const int n = (czl + 1) * a.cmy * a.cmx * 3;
+      for (int i = tid; i < n; i += kGzThreads) pbase[i] = P[i];
+    }
+  };
+
+#define BSI_GZ_EMIT(CZL, PH, LAST)                                                              \
+  {                                                                                           \
+    const int ph_ = (PH);                                                                     \
+    wave_lds_sync(); /* this wave's x-contraction of the previous plane is done with F */      \
+    _Pragma("unroll") for (int r = 0; r < kGzRows; ++r) {                                     \
+      F3 v;                                                                                   \
+      v.x = ph_ == 0 ? acc[0][r].x : ph_ == 1 ? acc[1][r].x : ph_ == 2 ? acc[2][r].x : acc[3][r].x; \
+      v.y = ph_ == 0 ? acc[0][r].y : ph_ == 1 ? acc[1][r].y : ph_ == 2 ? acc[2][r].y : acc[3][r].y; \
+      v.z = ph_ == 0 ? acc[0][r].z : ph_ == 1 ? acc[1][r].z : ph_ == 2 ? acc[2][r].z : acc[3][r].z; \
+      stf3(F + ((wave * kGzRows + r) * kGzBX + lane) * 3, v);                                 \
+      _Pragma("unroll") for (int k = 0; k < 4; ++k) {                                         \
+        acc[k][r].x = k == ph_ ? 0.f : acc[k][r].x;                                           \
+        acc[k][r].y = k == ph_ ? 0.f : acc[k][r].y;                                           \
+        acc[k][r].z = k == ph_ ? 0.f : acc[k][r].z;                                           \
+      }                                                                                       \
+    }                                                                                         \
+    wave_lds_sync();                                                                          \
+    contract((CZL), (LAST));                                                                  \
   }
+
+// One voxel plane Z from register set D: the z-accumulation with the plane's
+// weights (slot k takes B_{(k - ph) mod 4}), the loads of the plane two ahead
+// into the same registers (when LOAD), then the contraction of control plane
+// t when Z is the last plane of z-tile t (s >= 1: the next tile is t + 1).
+#define BSI_GZ_PLANE(D, Z, LOAD)                                                              \
+  {                                                                                           \
+    const int t_ = T.tile[2][(Z)];                                                            \
+    const int ph = (t_ - b.cz0) & 3;                                                          \
+    const float* wz = T.w[2] + 4 * (Z);                                                       \
+    const float w0 = wz[0], w1 = wz[1], w2 = wz[2], w3 = wz[3];                               \
+    const float ws[4] = {ph == 0 ? w0 : ph == 1 ? w3 : ph == 2 ? w2 : w1,                     \
+                         ph == 0 ? w1 : ph == 1 ? w0 : ph == 2 ? w3 : w2,                     \
+                         ph == 0 ? w2 : ph == 1 ? w1 : ph == 2 ? w0 : w3,                     \
+                         ph == 0 ? w3 : ph == 1 ? w2 : ph == 2 ? w1 : w0};                    \
+    _Pragma("unroll") for (int k = 0; k < 4; ++k)                                             \
+      _Pragma("unroll") for (int r = 0; r < kGzRows; ++r) {                                   \
+        acc[k][r].x = fmaf(ws[k], D[r].x, acc[k][r].x);                                       \
+        acc[k][r].y = fmaf(ws[k], D[r].y, acc[k][r].y);                                       \
+        acc[k][r].z = fmaf(ws[k], D[r].z, acc[k][r].z);                                       \
+      }                                                                                       \
+    if (LOAD) {                                                                               \
+      _Pragma("unroll") for (int r = 0; r < kGzRows; ++r) D[r] = ldf3_dfield<true>(ahead + off[r]); \
+    }                                                                                         \
+    ahead += plane;                                                                           \
+    if ((Z) + 1 < b.ze && T.tile[2][(Z) + 1] != t_) BSI_GZ_EMIT(t_ - b.cz0, ph, false)        \
+  }
+
+  // two register sets, each holding one plane's loads (as the aligned pass 1):
+  // in the main loop every load is unconditional, so waiting for one set
+  // leaves the other set's loads in flight
+  const float* base0 = dfield + (size_t)b.z0 * plane;
+  F3 d0[kGzRows], d1[kGzRows];
+#pragma unroll
+  for (int r = 0; r < kGzRows; ++r) d0[r] = ldf3_dfield<true>(base0 + off[r]);
+#pragma unroll
+  for (int r = 0; r < kGzRows; ++r) d1[r] = ldf3_dfield<true>(base0 + (b.ze - b.z0 > 1 ? plane : 0) + off[r]);
+  const float* ahead = base0 + 2 * plane;
+  int z = b.z0;
+  for (; z + 4 <= b.ze; z += 2) {
+    BSI_GZ_PLANE(d0, z, true)
+    BSI_GZ_PLANE(d1, z + 1, true)
+  }
+  for (; z < b.ze; z += 2) {
+    BSI_GZ_PLANE(d0, z, z + 2 < b.ze)
+    if (z + 1 < b.ze) BSI_GZ_PLANE(d1, z + 1, z + 3 < b.ze)
+  }
+#undef BSI_GZ_PLANE
+  const int t = T.tile[2][b.ze - 1];
+  // the brick's last four control planes, t .. t + 3, in ascending order
+#pragma unroll 1
+  for (int n = 0; n < 4; ++n) BSI_GZ_EMIT(t - b.cz0 + n, (t - b.cz0 + n) & 3, n == 3)
+#undef BSI_GZ_EMIT
+}
+
+// Pass 2: one thread per control point; a wave takes 64 points of one (cy, cz) row.
+__global__ __launch_bounds__(256) void gen_zf_pass2_kernel(const float* __restrict__ part, float* __restrict__ grad,
+                                                           GenGeom q, GenAdj a, GzTables T) {
+  const int nxb = (q.x.g + kWave - 1) / kWave, nyb = (q.y.g + 3) / 4;
+  int blk = blockIdx.x;
+  const int xb = blk % nxb;
+  blk /= nxb;
+  const int cy = (blk % nyb) * 4 + uniform(threadIdx.x / kWave);
+  const int cz = blk / nyb;
+  const int cx = xb * kWave + (threadIdx.x & (kWave - 1));
+  if (cy >= q.y.g || cx >= q.x.g) return;
+  // bricks meeting the support [first(c-3), first(c+1)) of each axis
+  const int xa = T.first[0][max(cx - 3, 0)] / kGzBX, xb2 = (T.first[0][cx + 1] - 1) / kGzBX;
+  const int ya = T.first[1][max(cy - 3, 0)] / kGzBY, yb2 = (T.first[1][cy + 1] - 1) / kGzBY;
+  const int za = max(cz - 3, 0) / a.kz, zb2 = min(cz, q.z.g - 4) / a.kz;
+  const size_t stride = (size_t)a.cmz * a.cmy * a.cmx * 3;
+  float sx = 0.f, sy = 0.f, sz = 0.f;
+  for (int bz = za; bz <= zb2; ++bz)
+    for (int by = ya; by <= yb2; ++by) {
+      const int cyl = cy - T.tile[1][by * kGzBY];
+      for (int bx = xa; bx <= xb2; ++bx) {
+        const int cxl = cx - T.tile[0][bx * kGzBX];
+        const size_t id = ((size_t)bz * a.nby + by) * a.nbx + bx;
+        const float* p = part + id * stride + ((size_t)((cz - bz * a.kz) * a.cmy + cyl) * a.cmx + cxl) * 3;
+        sx += p[0];
+        sy += p[1];
+        sz += p[2];
+      }
+    }
+  float* g = grad + (((size_t)cz * q.y.g + cy) * q.x.g + cx) * 3;
+  g[0] = sx;
+  g[1] = sy;
+  g[2] = sz;
 }
 
 constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
@@ -362,9 +550,36 @@ struct GenWork {
   int* tile[3];
   float* w[3];
   int* first[3];  // first voxel of every tile, per axis (g + 1 entries)
-  float* A;   // [nz][ny][gx][3]
-  float* Bm;  // [nz][gy][gx][3]
+  float* part;    // brick partials of the z-first adjoint
 };
+
+// Bricks of the z-first adjoint: about kGzTargetZ planes of whole z-tiles,
+// fewer (at least half as many) when that lets a brick's window of partials
+// fit the LDS stage.  A pure function of the geometry.
+GenAdj make_gen_adj(const GenGeom& q) {
+  GenAdj a;
+  a.nbx = (q.x.n + kGzBX - 1) / kGzBX;
+  a.nby = (q.y.n + kGzBY - 1) / kGzBY;
+  a.cmx = a.cmy = 0;
+  for (int bx = 0; bx < a.nbx; ++bx) {
+    const int x0 = bx * kGzBX, xe = std::min(q.x.n, x0 + kGzBX);
+    a.cmx = std::max(a.cmx, gen_tile(q.x, xe - 1) - gen_tile(q.x, x0) + 4);
+  }
+  for (int by = 0; by < a.nby; ++by) {
+    const int y0 = by * kGzBY, ye = std::min(q.y.n, y0 + kGzBY);
+    a.cmy = std::max(a.cmy, gen_tile(q.y, ye - 1) - gen_tile(q.y, y0) + 4);
+  }
+  const int tiles = q.z.g - 3;  // z-tiles holding voxels
+  int kz = std::max(1, (int)(kGzTargetZ / q.z.s));
+  kz = std::min(kz, tiles);
+  const int kfit = kGzStage / (a.cmy * a.cmx * 3) - 3;
+  if (kfit < kz && 2 * kfit >= kz) kz = kfit;
+  a.kz = kz;
+  a.nbz = (tiles + kz - 1) / kz;
+  a.cmz = kz + 3;
+  a.stage_all = (long)a.cmz * a.cmy * a.cmx * 3 <= kGzStage;
+  return a;
+}
 
 size_t gen_layout(const GenGeom& q, void* base, GenWork* wk) {
   char* p = static_cast<char*>(base);
@@ -380,10 +595,9 @@ size_t gen_layout(const GenGeom& q, void* base, GenWork* wk) {
     if (wk) wk->first[i] = reinterpret_cast<int*>(p + off);
     off += align256((size_t)(ax[i]->g + 1) * sizeof(int));
   }
-  if (wk) wk->A = reinterpret_cast<float*>(p + off);
-  off += align256((size_t)q.z.n * q.y.n * q.x.g * 3 * sizeof(float));
-  if (wk) wk->Bm = reinterpret_cast<float*>(p + off);
-  off += align256((size_t)q.z.n * q.y.g * q.x.g * 3 * sizeof(float));
+  const GenAdj a = make_gen_adj(q);
+  if (wk) wk->part = reinterpret_cast<float*>(p + off);
+  off += align256((size_t)a.nbx * a.nby * a.nbz * a.cmz * a.cmy * a.cmx * 3 * sizeof(float));
   return off;
 }
 
@@ -457,33 +671,36 @@ hipError_t launch_adjoint_general(const float* dfield, float* grad, const GenGeo
                                   hipStream_t s) {
   GenWork wk;
   gen_layout(q, workspace, &wk);
+  GenTables3 tp;
   const GenAxis* ax[3] = {&q.x, &q.y, &q.z};
   for (int i = 0; i < 3; ++i) {
-    hipLaunchKernelGGL(gen_table_kernel, dim3(blocks_for(ax[i]->n)), dim3(256), 0, s, *ax[i], wk.tile[i], wk.w[i]);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(gen_first_kernel, dim3(blocks_for(ax[i]->g + 1)), dim3(256), 0, s, *ax[i], wk.tile[i],
-                       wk.first[i]);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    tp.ax[i] = *ax[i];
+    tp.tile[i] = wk.tile[i];
+    tp.w[i] = wk.w[i];
+    tp.first[i] = wk.first[i];
+    tp.nb[i] = (int)blocks_for(ax[i]->n);
   }
-  // x: [nz*ny][nx] -> A [nz*ny][gx] by tile moments: kGxRows rows and kGxOut
-  // outputs per workgroup
-  hipError_t e;
-  const long rows = (long)q.z.n * q.y.n;
-  const long nseg = (q.x.g + kGxOut - 1) / kGxOut;
-  const long blocks = (rows + kGxRows - 1) / kGxRows * nseg;
-  if (blocks > 0x7fffffffL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(gen_gather_x_kernel, dim3((unsigned)blocks), dim3(kGxThreads), 0, s, dfield, wk.A, q.x,
-                     wk.first[0], wk.w[0], rows);
-  e = hipGetLastError();
+  hipLaunchKernelGGL(gen_tables3_kernel, dim3((unsigned)(tp.nb[0] + tp.nb[1] + tp.nb[2])), dim3(256), 0, s, tp);
+  if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+  for (int i = 0; i < 3; ++i) tp.nb[i] = (int)blocks_for(ax[i]->g + 1);
+  hipLaunchKernelGGL(gen_first3_kernel, dim3((unsigned)(tp.nb[0] + tp.nb[1] + tp.nb[2])), dim3(256), 0, s, tp);
+  if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
+  const GenAdj a = make_gen_adj(q);
+  GzTables T;
+  for (int i = 0; i < 3; ++i) {
+    T.tile[i] = wk.tile[i];
+    T.w[i] = wk.w[i];
+    T.first[i] = wk.first[i];
+  }
+  const long nbricks = (long)a.nbx * a.nby * a.nbz;
+  const int nxb = (q.x.g + kWave - 1) / kWave, nyb = (q.y.g + 3) / 4;
+  const long nblk = (long)nxb * nyb * q.z.g;
+  if (nbricks > 0x7fffffffL || nblk > 0x7fffffffL) return hipErrorInvalidValue;
+  const size_t lds = (size_t)gz_layout(a).total * sizeof(float);
+  hipLaunchKernelGGL(gen_zf_pass1_kernel, dim3((unsigned)nbricks), dim3(kGzThreads), lds, s, dfield, wk.part, q, a, T);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // y: [nz][ny][gx] -> Bm [nz][gy][gx]
-  hipLaunchKernelGGL(gen_gather_kernel, dim3(blocks_for((long)q.z.n * q.y.g * q.x.g)), dim3(256), 0, s, wk.A,
-                     wk.Bm, q.y, wk.tile[1], wk.first[1], wk.w[1], (long)q.z.n, q.x.g);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  // z: [1][nz][gy*gx] -> grad [gz][gy*gx]
-  hipLaunchKernelGGL(gen_gather_kernel, dim3(blocks_for((long)q.z.g * q.y.g * q.x.g)), dim3(256), 0, s, wk.Bm,
-                     grad, q.z, wk.tile[2], wk.first[2], wk.w[2], 1L, q.y.g * q.x.g);
+  hipLaunchKernelGGL(gen_zf_pass2_kernel, dim3((unsigned)nblk), dim3(256), 0, s, wk.part, grad, q, a, T);
   return hipGetLastError();
 }
 
