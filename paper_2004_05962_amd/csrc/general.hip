@@ -273,9 +273,10 @@ struct GenAdj {
   int stage_all;      // the whole window of partials fits the LDS stage
 };
 
-// LDS of one workgroup (floats): F, H[2], the x and y tables, the stage.
+// LDS of one workgroup (floats): F, H[2], the brick's x and y weight rows and
+// first-voxel tables, the stage.
 struct GzLayout {
-  int F, H, wx, tx, fx, wy, ty, fy, P, total;
+  int F, H, wx, fx, wy, fy, P, total;
 };
 __host__ __device__ inline GzLayout gz_layout(const GenAdj& a) {
   GzLayout L;
@@ -286,14 +287,10 @@ __host__ __device__ inline GzLayout gz_layout(const GenAdj& a) {
   o += 2 * kGzBY * a.cmx * 3;
   L.wx = o;
   o += kGzBX * 4;
-  L.tx = o;
-  o += kGzBX;
   L.fx = o;
   o += a.cmx + 4;
   L.wy = o;
   o += kGzBY * 4;
-  L.ty = o;
-  o += kGzBY;
   L.fy = o;
   o += a.cmy + 4;
   L.P = o;
@@ -335,7 +332,7 @@ __device__ __forceinline__ GzBrick gz_brick(const GenGeom& q, const GenAdj& a, c
   return b;
 }
 
-__global__ __launch_bounds__(kGzThreads) void gen_zf_pass1_kernel(const float* __restrict__ dfield,
+__global__ __launch_bounds__(kGzThreads) __attribute__((amdgpu_waves_per_eu(6))) void gen_zf_pass1_kernel(const float* __restrict__ dfield,
                                                                    float* __restrict__ part, GenGeom q, GenAdj a,
                                                                    GzTables T) {
   extern __shared__ float gz_smem[];
@@ -345,10 +342,8 @@ __global__ __launch_bounds__(kGzThreads) void gen_zf_pass1_kernel(const float* _
   const GzLayout L = gz_layout(a);
   float* F = gz_smem + L.F;
   float* wxT = gz_smem + L.wx;
-  int* txT = reinterpret_cast<int*>(gz_smem + L.tx);
   int* fxT = reinterpret_cast<int*>(gz_smem + L.fx);
   float* wyT = gz_smem + L.wy;
-  int* tyT = reinterpret_cast<int*>(gz_smem + L.ty);
   int* fyT = reinterpret_cast<int*>(gz_smem + L.fy);
   const GzBrick b = gz_brick(q, a, T, brick);
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = uniform(tid / kWave);
@@ -356,12 +351,10 @@ __global__ __launch_bounds__(kGzThreads) void gen_zf_pass1_kernel(const float* _
   // the brick's x and y tables; fxT[j] = first_x[cx0 + j - 3] (clamped at 0),
   // so output column cx0 + j takes the voxels [fxT[j], fxT[j + 4])
   if (tid < nxb) {
-    txT[tid] = T.tile[0][b.x0 + tid];
 #pragma unroll
     for (int l = 0; l < 4; ++l) wxT[4 * tid + l] = T.w[0][4 * (b.x0 + tid) + l];
   }
   if (tid < nyb) {
-    tyT[tid] = T.tile[1][b.y0 + tid];
 #pragma unroll
     for (int l = 0; l < 4; ++l) wyT[4 * tid + l] = T.w[1][4 * (b.y0 + tid) + l];
   }
@@ -393,15 +386,19 @@ __global__ __launch_bounds__(kGzThreads) void gen_zf_pass1_kernel(const float* _
       const int r = it / b.Cx, j = it - r * b.Cx;
       const int row = wave * kGzRows + r;
       if (row < nyb) {
-        const int c = b.cx0 + j;
-        const int va = max(fxT[j], b.x0) - b.x0, vb = min(fxT[j + 4], b.xe) - b.x0;
         float sx = 0.f, sy = 0.f, sz = 0.f;
         const float* Fr = F + row * kGzBX * 3;
-        for (int v = va; v < vb; ++v) {
-          const float wgt = wxT[4 * v + (c - txT[v])];
-          sx = fmaf(wgt, Fr[3 * v], sx);
-          sy = fmaf(wgt, Fr[3 * v + 1], sy);
-          sz = fmaf(wgt, Fr[3 * v + 2], sz);
+        // tiles c-3 .. c (weight index l = 3 .. 0): the voxels in ascending order
+#pragma unroll
+        for (int l = 3; l >= 0; --l) {
+          const int va = max(fxT[j + 3 - l], b.x0) - b.x0, vb = min(fxT[j + 4 - l], b.xe) - b.x0;
+#pragma unroll 2
+          for (int v = va; v < vb; ++v) {
+            const float wgt = wxT[4 * v + l];
+            sx = fmaf(wgt, Fr[3 * v], sx);
+            sy = fmaf(wgt, Fr[3 * v + 1], sy);
+            sz = fmaf(wgt, Fr[3 * v + 2], sz);
+          }
         }
         float* h = H + (row * a.cmx + j) * 3;
         h[0] = sx;
@@ -413,15 +410,18 @@ __global__ __launch_bounds__(kGzThreads) void gen_zf_pass1_kernel(const float* _
     // y: items (output row, output column) of the workgroup, each a run of rows
     for (int it = tid; it < b.Cy * b.Cx; it += kGzThreads) {
       const int i = it / b.Cx, j = it - i * b.Cx;
-      const int c = b.cy0 + i;
-      const int ya = max(fyT[i], b.y0) - b.y0, yb = min(fyT[i + 4], b.ye) - b.y0;
       float sx = 0.f, sy = 0.f, sz = 0.f;
-      for (int y = ya; y < yb; ++y) {
-        const float wgt = wyT[4 * y + (c - tyT[y])];
-        const float* h = H + (y * a.cmx + j) * 3;
-        sx = fmaf(wgt, h[0], sx);
-        sy = fmaf(wgt, h[1], sy);
-        sz = fmaf(wgt, h[2], sz);
+#pragma unroll
+      for (int l = 3; l >= 0; --l) {  // tiles c-3 .. c, rows ascending
+        const int ya = max(fyT[i + 3 - l], b.y0) - b.y0, yb = min(fyT[i + 4 - l], b.ye) - b.y0;
+#pragma unroll 2
+        for (int y = ya; y < yb; ++y) {
+          const float wgt = wyT[4 * y + l];
+          const float* h = H + (y * a.cmx + j) * 3;
+          sx = fmaf(wgt, h[0], sx);
+          sy = fmaf(wgt, h[1], sy);
+          sz = fmaf(wgt, h[2], sz);
+        }
       }
       float* dst = P + ((size_t)(czl * a.cmy + i) * a.cmx + j) * 3;
       dst[0] = sx;
@@ -456,13 +456,13 @@ __global__ __launch_bounds__(kGzThreads) void gen_zf_pass1_kernel(const float* _
   }
 
 // One voxel plane Z from register set D: the z-accumulation with the plane's
-// weights (slot k takes B_{(k - ph) mod 4}), the loads of the plane two ahead
-// into the same registers (when LOAD), then the contraction of control plane
-// t when Z is the last plane of z-tile t (s >= 1: the next tile is t + 1).
+// weights (slot k takes B_{(k - ph) mod 4}, ph = (t - cz0) mod 4 for the
+// plane's z-tile t), the loads of the plane two ahead into the same registers
+// (when LOAD), then, when Z is the last plane of tile t (tend = first_z[t+1]),
+// the contraction of control plane t; s >= 1, so the next tile is t + 1.
 #define BSI_GZ_PLANE(D, Z, LOAD)                                                              \
   {                                                                                           \
-    const int t_ = T.tile[2][(Z)];                                                            \
-    const int ph = (t_ - b.cz0) & 3;                                                          \
+    const int ph = (t - b.cz0) & 3;                                                           \
     const float* wz = T.w[2] + 4 * (Z);                                                       \
     const float w0 = wz[0], w1 = wz[1], w2 = wz[2], w3 = wz[3];                               \
     const float ws[4] = {ph == 0 ? w0 : ph == 1 ? w3 : ph == 2 ? w2 : w1,                     \
@@ -479,7 +479,11 @@ __global__ __launch_bounds__(kGzThreads) void gen_zf_pass1_kernel(const float* _
       _Pragma("unroll") for (int r = 0; r < kGzRows; ++r) D[r] = ldf3_dfield<true>(ahead + off[r]); \
     }                                                                                         \
     ahead += plane;                                                                           \
-    if ((Z) + 1 < b.ze && T.tile[2][(Z) + 1] != t_) BSI_GZ_EMIT(t_ - b.cz0, ph, false)        \
+    if ((Z) + 1 == tend && (Z) + 1 < b.ze) {                                                  \
+      BSI_GZ_EMIT(t - b.cz0, ph, false)                                                       \
+      ++t;                                                                                    \
+      tend = T.first[2][t + 1];                                                               \
+    }                                                                                         \
   }
 
   // two register sets, each holding one plane's loads (as the aligned pass 1):
@@ -492,6 +496,8 @@ __global__ __launch_bounds__(kGzThreads) void gen_zf_pass1_kernel(const float* _
 #pragma unroll
   for (int r = 0; r < kGzRows; ++r) d1[r] = ldf3_dfield<true>(base0 + (b.ze - b.z0 > 1 ? plane : 0) + off[r]);
   const float* ahead = base0 + 2 * plane;
+  int t = b.cz0;                    // the z-tile of the plane at hand (the brick starts on a tile)
+  int tend = T.first[2][t + 1];     // its end
   int z = b.z0;
   for (; z + 4 <= b.ze; z += 2) {
     BSI_GZ_PLANE(d0, z, true)
@@ -502,7 +508,6 @@ __global__ __launch_bounds__(kGzThreads) void gen_zf_pass1_kernel(const float* _
     if (z + 1 < b.ze) BSI_GZ_PLANE(d1, z + 1, z + 3 < b.ze)
   }
 #undef BSI_GZ_PLANE
-  const int t = T.tile[2][b.ze - 1];
   // the brick's last four control planes, t .. t + 3, in ascending order
 #pragma unroll 1
   for (int n = 0; n < 4; ++n) BSI_GZ_EMIT(t - b.cz0 + n, (t - b.cz0 + n) & 3, n == 3)
