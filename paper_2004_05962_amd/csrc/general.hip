@@ -215,33 +215,30 @@ struct GenTables3 {
   int nb[3];  // workgroups per axis
 };
 
+// Thread k of an axis's workgroups writes entry k of its tables: tile[k] =
+// i(k) and w[k] = B(u(k)) for k < n, and first[k] = min{v : i(v) >= k} for
+// k <= g (first[g] = n), found by bisection on the exact i(v), so the three
+// tables need no order between them.
 __global__ __launch_bounds__(256) void gen_tables3_kernel(GenTables3 p) {
   int blk = blockIdx.x, i = 0;
   while (i < 2 && blk >= p.nb[i]) blk -= p.nb[i++];
   const GenAxis a = p.ax[i];
-  const int v = blk * 256 + threadIdx.x;
-  if (v >= a.n) return;
-  float b[4];
-  p.tile[i][v] = gen_weights(a, v, b);
+  const int k = blk * 256 + threadIdx.x;
+  if (k < a.n) {
+    float b[4];
+    p.tile[i][k] = gen_weights(a, k, b);
 #pragma unroll
-  for (int l = 0; l < 4; ++l) p.w[i][4 * v + l] = b[l];
-}
-
-// First voxel of every tile of each axis (one launch for the three axes).
-__global__ __launch_bounds__(256) void gen_first3_kernel(GenTables3 p) {
-  int blk = blockIdx.x, i = 0;
-  while (i < 2 && blk >= p.nb[i]) blk -= p.nb[i++];
-  const GenAxis a = p.ax[i];
-  const int t = blk * 256 + threadIdx.x;
-  if (t > a.g) return;
-  const int* tile = p.tile[i];
-  int lo = 0, hi = a.n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (tile[mid] < t) lo = mid + 1;
-    else hi = mid;
+    for (int l = 0; l < 4; ++l) p.w[i][4 * k + l] = b[l];
   }
-  p.first[i][t] = lo;
+  if (k <= a.g) {
+    int lo = 0, hi = a.n;  // i(v) is nondecreasing in v
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (gen_tile(a, mid) < k) lo = mid + 1;
+      else hi = mid;
+    }
+    p.first[i][k] = lo;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -332,6 +329,9 @@ __device__ __forceinline__ GzBrick gz_brick(const GenGeom& q, const GenAdj& a, c
   return b;
 }
 
+// XTiles: every brick meets at most 16 x-tiles (window width cmx <= 19), so
+// the x-contraction runs on tile lanes.
+template <bool XTiles>
 __global__ __launch_bounds__(kGzThreads) __attribute__((amdgpu_waves_per_eu(6))) void gen_zf_pass1_kernel(const float* __restrict__ dfield,
                                                                    float* __restrict__ part, GenGeom q, GenAdj a,
                                                                    GzTables T) {
@@ -381,52 +381,81 @@ __global__ __launch_bounds__(kGzThreads) __attribute__((amdgpu_waves_per_eu(6)))
   // cleared, then the x- and y-contractions into the partials
   auto contract = [&](int czl, bool last) {
     float* H = gz_smem + L.H + (czl & 1) * kGzBY * a.cmx * 3;
-    // x: items (row of this wave, output column), each a run of the row's voxels
-    for (int it = lane; it < kGzRows * b.Cx; it += kWave) {
-      const int r = it / b.Cx, j = it - r * b.Cx;
-      const int row = wave * kGzRows + r;
-      if (row < nyb) {
-        float sx = 0.f, sy = 0.f, sz = 0.f;
-        const float* Fr = F + row * kGzBX * 3;
-        // tiles c-3 .. c (weight index l = 3 .. 0): the voxels in ascending order
+    // x.  Tile lanes when the brick meets at most 16 x-tiles (as in the aligned
+    // pass 1): lane (rr, t) of this wave forms the 4 moments of tile cx0 + t
+    // of its row rr, M_l = sum over the tile's voxels (ascending) of
+    // B_l(u(v)) F[v], and DPP row rotations combine them into the window
+    // columns, H[j] = sum_l M_l(tile j - l).  Otherwise one lane per (row,
+    // column), summing the column's voxels tile by tile.
+    if constexpr (XTiles) {
+      const int rr = lane / kAdjTiles, tt = lane % kAdjTiles;
+      const int row = wave * kGzRows + rr;
+      const bool rowok = rr < kGzRows && row < nyb;
+      F3 M[4];
 #pragma unroll
-        for (int l = 3; l >= 0; --l) {
-          const int va = max(fxT[j + 3 - l], b.x0) - b.x0, vb = min(fxT[j + 4 - l], b.xe) - b.x0;
+      for (int l = 0; l < 4; ++l) M[l] = F3{0.f, 0.f, 0.f};
+      if (rowok && tt < b.Cx - 3) {
+        const int va = max(fxT[tt + 3], b.x0) - b.x0, vb = min(fxT[tt + 4], b.xe) - b.x0;
+        const float* Fr = F + row * kGzBX * 3;
 #pragma unroll 2
-          for (int v = va; v < vb; ++v) {
-            const float wgt = wxT[4 * v + l];
-            sx = fmaf(wgt, Fr[3 * v], sx);
-            sy = fmaf(wgt, Fr[3 * v + 1], sy);
-            sz = fmaf(wgt, Fr[3 * v + 2], sz);
+        for (int v = va; v < vb; ++v) adj_moment_step(wxT + 4 * v, ldf3(Fr + 3 * v), M);
+      }
+      F3 cm, cw;
+      adj_combine(tt, M, cm, cw);  // every lane of the wave takes part
+      if (rowok) {
+        float* hrow = H + row * a.cmx * 3;
+        if (tt < b.Cx) stf3(hrow + tt * 3, cm);
+        if (tt < 3 && kAdjTiles + tt < b.Cx) stf3(hrow + (kAdjTiles + tt) * 3, cw);
+      }
+    } else {
+      for (int it = lane; it < kGzRows * b.Cx; it += kWave) {
+        const int r = it / b.Cx, j = it - r * b.Cx;
+        const int row = wave * kGzRows + r;
+        if (row < nyb) {
+          float sx = 0.f, sy = 0.f, sz = 0.f;
+          const float* Fr = F + row * kGzBX * 3;
+          // tiles c-3 .. c (weight index l = 3 .. 0): the voxels in ascending order
+#pragma unroll
+          for (int l = 3; l >= 0; --l) {
+            const int va = max(fxT[j + 3 - l], b.x0) - b.x0, vb = min(fxT[j + 4 - l], b.xe) - b.x0;
+#pragma unroll 2
+            for (int v = va; v < vb; ++v) {
+              const float wgt = wxT[4 * v + l];
+              sx = fmaf(wgt, Fr[3 * v], sx);
+              sy = fmaf(wgt, Fr[3 * v + 1], sy);
+              sz = fmaf(wgt, Fr[3 * v + 2], sz);
+            }
           }
+          stf3(H + (row * a.cmx + j) * 3, F3{sx, sy, sz});
         }
-        float* h = H + (row * a.cmx + j) * 3;
-        h[0] = sx;
-        h[1] = sy;
-        h[2] = sz;
       }
     }
     __syncthreads();
-    // y: items (output row, output column) of the workgroup, each a run of rows
-    for (int it = tid; it < b.Cy * b.Cx; it += kGzThreads) {
-      const int i = it / b.Cx, j = it - i * b.Cx;
-      float sx = 0.f, sy = 0.f, sz = 0.f;
+    // y, on y-tile lanes (a brick of 16 rows meets at most 16 y-tiles): lane
+    // (c4, ty) of wave w takes window column 4 w + c4 (then + 32 ...) and
+    // y-tile cy0 + ty, forms N_m = sum over the tile's rows (ascending) of
+    // B_m(v(y)) H[y][column], and the rotations give window rows ty and
+    // (ty < 3) 16 + ty.
+    {
+      const int c4 = lane / kAdjTiles, ty = lane % kAdjTiles;
+      const int nty = b.Cy - 3;
+      for (int c0 = wave * 4; c0 < b.Cx; c0 += kGzWaves * 4) {  // uniform over the wave
+        const int j = c0 + c4;
+        F3 N[4];
 #pragma unroll
-      for (int l = 3; l >= 0; --l) {  // tiles c-3 .. c, rows ascending
-        const int ya = max(fyT[i + 3 - l], b.y0) - b.y0, yb = min(fyT[i + 4 - l], b.ye) - b.y0;
+        for (int m = 0; m < 4; ++m) N[m] = F3{0.f, 0.f, 0.f};
+        if (j < b.Cx && ty < nty) {
+          const int ya = max(fyT[ty + 3], b.y0) - b.y0, yb = min(fyT[ty + 4], b.ye) - b.y0;
 #pragma unroll 2
-        for (int y = ya; y < yb; ++y) {
-          const float wgt = wyT[4 * y + l];
-          const float* h = H + (y * a.cmx + j) * 3;
-          sx = fmaf(wgt, h[0], sx);
-          sy = fmaf(wgt, h[1], sy);
-          sz = fmaf(wgt, h[2], sz);
+          for (int y = ya; y < yb; ++y) adj_moment_step(wyT + 4 * y, ldf3(H + (y * a.cmx + j) * 3), N);
+        }
+        F3 gm, gw;
+        adj_combine(ty, N, gm, gw);  // every lane of the wave takes part
+        if (j < b.Cx) {
+          if (ty < b.Cy) stf3(P + ((size_t)(czl * a.cmy + ty) * a.cmx + j) * 3, gm);
+          if (ty < 3 && kAdjTiles + ty < b.Cy) stf3(P + ((size_t)(czl * a.cmy + kAdjTiles + ty) * a.cmx + j) * 3, gw);
         }
       }
-      float* dst = P + ((size_t)(czl * a.cmy + i) * a.cmx + j) * 3;
-      dst[0] = sx;
-      dst[1] = sy;
-      dst[2] = sz;
     }
     if (a.stage_all && last) {
       __syncthreads();
@@ -683,12 +712,9 @@ hipError_t launch_adjoint_general(const float* dfield, float* grad, const GenGeo
     tp.tile[i] = wk.tile[i];
     tp.w[i] = wk.w[i];
     tp.first[i] = wk.first[i];
-    tp.nb[i] = (int)blocks_for(ax[i]->n);
+    tp.nb[i] = (int)blocks_for(std::max(ax[i]->n, ax[i]->g + 1));
   }
   hipLaunchKernelGGL(gen_tables3_kernel, dim3((unsigned)(tp.nb[0] + tp.nb[1] + tp.nb[2])), dim3(256), 0, s, tp);
-  if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
-  for (int i = 0; i < 3; ++i) tp.nb[i] = (int)blocks_for(ax[i]->g + 1);
-  hipLaunchKernelGGL(gen_first3_kernel, dim3((unsigned)(tp.nb[0] + tp.nb[1] + tp.nb[2])), dim3(256), 0, s, tp);
   if (hipError_t e = hipGetLastError(); e != hipSuccess) return e;
   const GenAdj a = make_gen_adj(q);
   GzTables T;
@@ -702,7 +728,12 @@ hipError_t launch_adjoint_general(const float* dfield, float* grad, const GenGeo
   const long nblk = (long)nxb * nyb * q.z.g;
   if (nbricks > 0x7fffffffL || nblk > 0x7fffffffL) return hipErrorInvalidValue;
   const size_t lds = (size_t)gz_layout(a).total * sizeof(float);
-  hipLaunchKernelGGL(gen_zf_pass1_kernel, dim3((unsigned)nbricks), dim3(kGzThreads), lds, s, dfield, wk.part, q, a, T);
+  if (a.cmx - 3 <= kAdjTiles)
+    hipLaunchKernelGGL(gen_zf_pass1_kernel<true>, dim3((unsigned)nbricks), dim3(kGzThreads), lds, s, dfield, wk.part, q,
+                       a, T);
+  else
+    hipLaunchKernelGGL(gen_zf_pass1_kernel<false>, dim3((unsigned)nbricks), dim3(kGzThreads), lds, s, dfield, wk.part,
+                       q, a, T);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(gen_zf_pass2_kernel, dim3((unsigned)nblk), dim3(256), 0, s, wk.part, grad, q, a, T);
