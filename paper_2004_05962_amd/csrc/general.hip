@@ -28,66 +28,9 @@
 #include <cmath>
 
 #include "adjoint_device.h"
-#include "bsi_internal.h"
+#include "general_device.h"
 
 namespace bsi {
-
-// a + b = s + e exactly (Knuth's two-sum; round to nearest, no overflow).
-__host__ __device__ inline void two_sum(float a, float b, float& s, float& e) {
-  s = a + b;
-  const float bb = s - a;
-  e = (a - (s - bb)) + (b - bb);
-}
-
-// Exact sign of D(i) = (x - o) - i s for integers 0 <= x, |i| < 2^24, and the
-// FP32 value of D rounded from its exact expansion.  x - o = A + a and i s =
-// P + p are error-free; growing the nonoverlapping expansion (a, A) by -p and
-// then by -P (Shewchuk's grow-expansion) gives four nonoverlapping components
-// whose largest nonzero one carries the sign of the exact sum.
-__host__ __device__ inline int gen_residual(float X, float o, float s, int i, float& D) {
-  float A, a;
-  two_sum(X, -o, A, a);
-  const float I = (float)i;
-  const float P = I * s;
-  const float p = fmaf(I, s, -P);
-  float Q, h0, h1, k0, k1, k2;
-  two_sum(-p, a, Q, h0);
-  two_sum(Q, A, Q, h1);
-  const float h2 = Q;
-  two_sum(-P, h0, Q, k0);
-  two_sum(Q, h1, Q, k1);
-  two_sum(Q, h2, Q, k2);
-  const float k3 = Q;
-  D = k3 + k2;
-  const float top = k3 != 0.f ? k3 : k2 != 0.f ? k2 : k1 != 0.f ? k1 : k0;
-  return top > 0.f ? 1 : top < 0.f ? -1 : 0;
-}
-
-// Window start i = floor((v - o)/s) of voxel v (exact) and u = (v - o)/s - i
-// in FP32.  The FP32 quotient is within 1/8 of the exact one for v < 2^21, so
-// the floor is its floor, one below or one above; the exact residual decides.
-__host__ __device__ inline int gen_locate(const GenAxis& a, int v, float& u) {
-  const float X = (float)v;
-  int i = (int)floorf((X - a.o) / a.s);
-  float D;
-  if (gen_residual(X, a.o, a.s, i, D) < 0) {
-    --i;
-    (void)gen_residual(X, a.o, a.s, i, D);
-  } else {
-    float D1;
-    if (gen_residual(X, a.o, a.s, i + 1, D1) >= 0) {
-      ++i;
-      D = D1;
-    }
-  }
-  u = D / a.s;
-  return i;
-}
-
-__host__ __device__ inline int gen_tile(const GenAxis& a, int v) {
-  float u;
-  return gen_locate(a, v, u);
-}
 
 namespace {
 
@@ -255,80 +198,6 @@ __global__ __launch_bounds__(256) void gen_tables3_kernel(GenTables3 p) {
 // over y the same way, giving the brick's partial of that plane.  Pass 2
 // sums, per control point, the partials of the bricks meeting its support in
 // fixed order.  No atomics.
-constexpr int kGzBX = kWave;             // brick width (voxels)
-constexpr int kGzRows = 2;               // rows per lane
-constexpr int kGzWaves = 8;
-constexpr int kGzBY = kGzRows * kGzWaves;  // brick height (rows)
-constexpr int kGzThreads = kGzWaves * kWave;
-constexpr int kGzTargetZ = 48;           // about this many voxel planes per brick
-constexpr int kGzStage = 6144;           // floats of staged partials (24 KB)
-
-struct GenAdj {
-  int nbx, nby, nbz;  // bricks per axis
-  int kz;             // z-tiles per brick
-  int cmx, cmy, cmz;  // window extents (the largest over the bricks)
-  int stage_all;      // the whole window of partials fits the LDS stage
-};
-
-// LDS of one workgroup (floats): F, H[2], the brick's x and y weight rows and
-// first-voxel tables, the stage.
-struct GzLayout {
-  int F, H, wx, fx, wy, fy, P, total;
-};
-__host__ __device__ inline GzLayout gz_layout(const GenAdj& a) {
-  GzLayout L;
-  int o = 0;
-  L.F = o;
-  o += kGzBY * kGzBX * 3;
-  L.H = o;
-  o += 2 * kGzBY * a.cmx * 3;
-  L.wx = o;
-  o += kGzBX * 4;
-  L.fx = o;
-  o += a.cmx + 4;
-  L.wy = o;
-  o += kGzBY * 4;
-  L.fy = o;
-  o += a.cmy + 4;
-  L.P = o;
-  o += a.stage_all ? a.cmz * a.cmy * a.cmx * 3 : 0;
-  L.total = o;
-  return L;
-}
-
-struct GzTables {
-  const int* tile[3];
-  const float* w[3];
-  const int* first[3];
-};
-
-// Brick (bx, by, bz): its voxel range and the first control index of its window per axis.
-struct GzBrick {
-  int x0, xe, y0, ye, z0, ze;
-  int cx0, cy0, cz0;
-  int Cx, Cy;
-};
-
-__device__ __forceinline__ GzBrick gz_brick(const GenGeom& q, const GenAdj& a, const GzTables& T, int id) {
-  GzBrick b;
-  const int bx = id % a.nbx;
-  const int r = id / a.nbx;
-  const int by = r % a.nby;
-  const int bz = r / a.nby;
-  b.x0 = bx * kGzBX;
-  b.xe = min(q.x.n, b.x0 + kGzBX);
-  b.y0 = by * kGzBY;
-  b.ye = min(q.y.n, b.y0 + kGzBY);
-  b.cz0 = bz * a.kz;
-  b.z0 = T.first[2][b.cz0];
-  b.ze = T.first[2][min(b.cz0 + a.kz, q.z.g - 3)];
-  b.cx0 = T.tile[0][b.x0];
-  b.Cx = T.tile[0][b.xe - 1] - b.cx0 + 4;
-  b.cy0 = T.tile[1][b.y0];
-  b.Cy = T.tile[1][b.ye - 1] - b.cy0 + 4;
-  return b;
-}
-
 // XTiles: every brick meets at most 16 x-tiles (window width cmx <= 19), so
 // the x-contraction runs on tile lanes.
 template <bool XTiles>
@@ -555,9 +424,9 @@ __global__ __launch_bounds__(256) void gen_zf_pass2_kernel(const float* __restri
   const int cx = xb * kWave + (threadIdx.x & (kWave - 1));
   if (cy >= q.y.g || cx >= q.x.g) return;
   // bricks meeting the support [first(c-3), first(c+1)) of each axis
-  const int xa = T.first[0][max(cx - 3, 0)] / kGzBX, xb2 = (T.first[0][cx + 1] - 1) / kGzBX;
-  const int ya = T.first[1][max(cy - 3, 0)] / kGzBY, yb2 = (T.first[1][cy + 1] - 1) / kGzBY;
-  const int za = max(cz - 3, 0) / a.kz, zb2 = min(cz, q.z.g - 4) / a.kz;
+  const GzSpan spx = gz_span(T.first[0], cx, kGzBX), spy = gz_span(T.first[1], cy, kGzBY),
+               spz = gz_span_z(a, cz, q.z.g);
+  const int xa = spx.lo, xb2 = spx.hi, ya = spy.lo, yb2 = spy.hi, za = spz.lo, zb2 = spz.hi;
   const size_t stride = (size_t)a.cmz * a.cmy * a.cmx * 3;
   float sx = 0.f, sy = 0.f, sz = 0.f;
   for (int bz = za; bz <= zb2; ++bz)
@@ -586,34 +455,6 @@ struct GenWork {
   int* first[3];  // first voxel of every tile, per axis (g + 1 entries)
   float* part;    // brick partials of the z-first adjoint
 };
-
-// Bricks of the z-first adjoint: about kGzTargetZ planes of whole z-tiles,
-// fewer (at least half as many) when that lets a brick's window of partials
-// fit the LDS stage.  A pure function of the geometry.
-GenAdj make_gen_adj(const GenGeom& q) {
-  GenAdj a;
-  a.nbx = (q.x.n + kGzBX - 1) / kGzBX;
-  a.nby = (q.y.n + kGzBY - 1) / kGzBY;
-  a.cmx = a.cmy = 0;
-  for (int bx = 0; bx < a.nbx; ++bx) {
-    const int x0 = bx * kGzBX, xe = std::min(q.x.n, x0 + kGzBX);
-    a.cmx = std::max(a.cmx, gen_tile(q.x, xe - 1) - gen_tile(q.x, x0) + 4);
-  }
-  for (int by = 0; by < a.nby; ++by) {
-    const int y0 = by * kGzBY, ye = std::min(q.y.n, y0 + kGzBY);
-    a.cmy = std::max(a.cmy, gen_tile(q.y, ye - 1) - gen_tile(q.y, y0) + 4);
-  }
-  const int tiles = q.z.g - 3;  // z-tiles holding voxels
-  int kz = std::max(1, (int)(kGzTargetZ / q.z.s));
-  kz = std::min(kz, tiles);
-  const int kfit = kGzStage / (a.cmy * a.cmx * 3) - 3;
-  if (kfit < kz && 2 * kfit >= kz) kz = kfit;
-  a.kz = kz;
-  a.nbz = (tiles + kz - 1) / kz;
-  a.cmz = kz + 3;
-  a.stage_all = (long)a.cmz * a.cmy * a.cmx * 3 <= kGzStage;
-  return a;
-}
 
 size_t gen_layout(const GenGeom& q, void* base, GenWork* wk) {
   char* p = static_cast<char*>(base);

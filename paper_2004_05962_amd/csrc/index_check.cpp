@@ -12,6 +12,7 @@
 
 #include "adjoint_device.h"
 #include "bsi_internal.h"
+#include "general_device.h"
 
 namespace bsi {
 namespace {
@@ -218,6 +219,90 @@ bool check_forward(const VolGeom& g, Check& ck) {
          check_forward_span<3>(g, ck) && check_forward_span<1>(g, ck) && check_forward_batched(g, ck);
 }
 
+// The z-first adjoint of the real-spacing grid (general.hip): its bricks,
+// LDS request, table reads, partial offsets and pass-2 spans, with host
+// tables built by the same exact window-start function the device uses.
+bool check_general_adjoint(const GenGeom& q, Check& ck) {
+  const GenAxis* ax[3] = {&q.x, &q.y, &q.z};
+  std::vector<int> tile[3], first[3];
+  for (int i = 0; i < 3; ++i) {
+    const GenAxis& A = *ax[i];
+    tile[i].resize((size_t)A.n);
+    for (int v = 0; v < A.n; ++v) tile[i][(size_t)v] = gen_tile(A, v);
+    REQUIRE(tile[i][0] == 0 && tile[i][(size_t)A.n - 1] == A.g - 4, "window starts span the grid");
+    for (int v = 1; v < A.n; ++v) {
+      const int d = tile[i][(size_t)v] - tile[i][(size_t)v - 1];
+      REQUIRE(d == 0 || d == 1, "window starts step by 0 or 1 (spacing >= 1)");
+    }
+    first[i].resize((size_t)A.g + 1);
+    for (int t = 0; t <= A.g; ++t) {
+      int lo = 0, hi = A.n;
+      while (lo < hi) {
+        const int mid = (lo + hi) / 2;
+        if (tile[i][(size_t)mid] < t) lo = mid + 1;
+        else hi = mid;
+      }
+      first[i][(size_t)t] = lo;
+    }
+  }
+  GzTables T;
+  for (int i = 0; i < 3; ++i) {
+    T.tile[i] = tile[i].data();
+    T.w[i] = nullptr;
+    T.first[i] = first[i].data();
+  }
+  const GenAdj a = make_gen_adj(q);
+  const GzLayout L = gz_layout(a);
+  REQUIRE((size_t)L.total * sizeof(float) <= 65536, "pass-1 LDS request within 64 KB");
+  REQUIRE(a.kz >= 1 && a.nbz * a.kz >= q.z.g - 3 && (a.nbz - 1) * a.kz < q.z.g - 3, "z-bricks cover the z-tiles");
+  const bool xtiles = a.cmx - 3 <= kAdjTiles;
+  const long nbricks = (long)a.nbx * a.nby * a.nbz;
+  REQUIRE(nbricks < (1L << 31), "pass-1 grid");
+  std::vector<int> last((size_t)a.nbz);
+  for (long id = 0; id < nbricks; ++id) {
+    const GzBrick b = gz_brick(q, a, T, (int)id);
+    REQUIRE(b.x0 < b.xe && b.xe - b.x0 <= kGzBX && b.y0 < b.ye && b.ye - b.y0 <= kGzBY, "brick inside the volume");
+    REQUIRE(b.z0 < b.ze && b.ze <= q.z.n, "brick planes inside the volume");
+    REQUIRE(b.Cx <= a.cmx && b.Cy <= a.cmy, "window within the partials' extents");
+    REQUIRE(b.Cx + 4 <= kGzThreads && b.Cy + 4 <= kGzThreads, "table fill within the workgroup");
+    REQUIRE(b.cx0 + b.Cx <= q.x.g && b.cy0 + b.Cy <= q.y.g, "first-voxel reads within the tables");
+    REQUIRE(!xtiles || b.Cx - 3 <= kAdjTiles, "x-tiles within one row of tile lanes");
+    REQUIRE(b.Cy - 3 <= kAdjTiles, "y-tiles within one row of tile lanes");
+    const int tl = tile[2][(size_t)b.ze - 1];
+    REQUIRE(tl - b.cz0 >= 0 && tl - b.cz0 + 3 < a.cmz, "the brick's last control plane within its window");
+    if (a.stage_all) REQUIRE((tl - b.cz0 + 4) * a.cmy * a.cmx * 3 <= kGzStage, "staged partials within the stage");
+    last[(size_t)(id / ((long)a.nbx * a.nby))] = tl;
+  }
+  // pass 2: every brick a control point reads holds it in its window
+  for (int c = 0; c < q.x.g; ++c) {
+    const GzSpan sp = gz_span(T.first[0], c, kGzBX);
+    REQUIRE(0 <= sp.lo && sp.lo <= sp.hi && sp.hi < a.nbx, "x span");
+    for (int bx = sp.lo; bx <= sp.hi; ++bx) {
+      const GzBrick b = gz_brick(q, a, T, bx);
+      REQUIRE(c - b.cx0 >= 0 && c - b.cx0 < b.Cx, "pass 2 reads an x column outside the brick's window");
+    }
+  }
+  for (int c = 0; c < q.y.g; ++c) {
+    const GzSpan sp = gz_span(T.first[1], c, kGzBY);
+    REQUIRE(0 <= sp.lo && sp.lo <= sp.hi && sp.hi < a.nby, "y span");
+    for (int by = sp.lo; by <= sp.hi; ++by) {
+      const GzBrick b = gz_brick(q, a, T, by * a.nbx);
+      REQUIRE(c - b.cy0 >= 0 && c - b.cy0 < b.Cy, "pass 2 reads a y row outside the brick's window");
+    }
+  }
+  for (int c = 0; c < q.z.g; ++c) {
+    const GzSpan sp = gz_span_z(a, c, q.z.g);
+    REQUIRE(0 <= sp.lo && sp.lo <= sp.hi && sp.hi < a.nbz, "z span");
+    for (int bz = sp.lo; bz <= sp.hi; ++bz) {
+      const int czl = c - bz * a.kz;
+      REQUIRE(czl >= 0 && czl <= last[(size_t)bz] - bz * a.kz + 3, "pass 2 reads a control plane the brick did not emit");
+    }
+  }
+  const long nblk = (long)((q.x.g + kWave - 1) / kWave) * ((q.y.g + 3) / 4) * q.z.g;
+  REQUIRE(nblk < (1L << 31), "pass-2 grid");
+  return true;
+}
+
 }  // namespace
 }  // namespace bsi
 
@@ -234,6 +319,21 @@ int bsi_check_indices(const int32_t dims[3], const int32_t spacing[3], char* msg
   }
   Check ck;
   check_adjoints(g, ck) && check_forward(g, ck);
+  std::snprintf(msg, msglen, "%s", ck.msg.c_str());
+  return ck.ok ? 0 : 1;
+}
+
+// 0: every check of the real-spacing adjoint passed; 1: one failed; -1: invalid geometry.
+int bsi_check_general_indices(const int32_t dims[3], const float spacing[3], const float origin[3], char* msg,
+                              int msglen) {
+  GenGeom q;
+  VolGeom g;
+  if (make_gen_geom(dims, spacing, origin, &q, &g)) {
+    std::snprintf(msg, msglen, "invalid geometry");
+    return -1;
+  }
+  Check ck;
+  check_general_adjoint(q, ck);
   std::snprintf(msg, msglen, "%s", ck.msg.c_str());
   return ck.ok ? 0 : 1;
 }

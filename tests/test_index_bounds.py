@@ -70,3 +70,33 @@ def test_batched_item_loops_end_and_cover():
     L.bsi_check_batch_items.restype = ctypes.c_int
     msg = ctypes.create_string_buffer(512)
     assert L.bsi_check_batch_items(msg, 512) == 0, msg.value.decode()
+
+
+GENERAL = [
+    ((64, 48, 40), (4.7, 5.3, 5.1), (-1.5, 0.0, -2.25)),
+    ((37, 29, 23), (2.5, 3.25, 1.75), (-0.5, -3.0, -1.25)),
+    ((130, 9, 11), (1.0, 2.2, 3.3), (0.0, -1.1, -0.2)),
+    ((70, 45, 20), (63.5, 7.75, 10.0), (-63.0, -2.5, -9.5)),
+    ((20, 20, 20), (4.0, 4.0, 4.0), (0.0, 0.0, 0.0)),
+    ((192, 9, 7), (5.5, 2.0, 3.0), (-1.0, 0.0, -0.5)),
+    ((96, 80, 72), (4.3, 5.6, 3.1), (-2.0, -0.7, -1.0)),
+    ((512, 512, 256), (5.3, 4.7, 5.1), (-2.5, -0.25, -4.0)),
+    ((1, 1, 1), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0)),
+    ((300, 3, 200), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0)),
+    ((65, 17, 50), (64.0, 64.0, 64.0), (-63.9, -0.5, 0.0)),
+    ((257, 130, 97), (4.31, 1.07, 12.9), (-4.3, -1.0, -0.01)),
+]
+
+
+@pytest.mark.parametrize("dims,spacing,origin", GENERAL)
+def test_general_adjoint_indices(dims, spacing, origin):
+    """The real-spacing adjoint's bricks, LDS request, table reads, partial
+    offsets and pass-2 spans, over geometries with unit, fractional and coarse
+    spacings (host tables from the device's own window-start function)."""
+    L = ctypes.CDLL(LIB)
+    f3 = ctypes.c_float * 3
+    L.bsi_check_general_indices.argtypes = [ctypes.POINTER(ctypes.c_int32), f3, f3, ctypes.c_char_p, ctypes.c_int]
+    L.bsi_check_general_indices.restype = ctypes.c_int
+    msg = ctypes.create_string_buffer(512)
+    rc = L.bsi_check_general_indices((ctypes.c_int32 * 3)(*dims), f3(*spacing), f3(*origin), msg, 512)
+    assert rc == 0, msg.value.decode()
