@@ -287,13 +287,15 @@ int32_t bsi_batch_bind(bsi_batch* plan, const float* const* grids, float* const*
                        const float* const* dfields, float* const* grid_grads);
 
 /* Choose the plan's schedule by timing it on `stream` with the bound buffers
-   (the outputs are written while timing).  A schedule sets eight knobs: the
+   (the outputs are written while timing).  A schedule sets nine knobs: the
    forward's workgroup shape (rows x 64-voxel strips: 4x1, 2x2, 8x1), its
    items per volume (z split target 512, 2048, 8192), the persistent grid of
    each pass in workgroups per CU (forward 0/2/4/8, pass 1 0/1/2/3, pass 2 0/8;
    0 = one workgroup per item), the number of streams the pass-1 launches
    spread over (1, 2, 4), whether the forward runs beside the adjoint or before
-   it, and whether the forward's stores are ordinary or non-temporal.  The search is a coordinate descent from the current schedule, each
+   it, whether the forward's stores are ordinary or non-temporal, and whether
+   pass 1 runs one launch per x-spacing class or one launch for all the
+   spacings 4..12 (a kernel that takes the spacing at run time).  The search is a coordinate descent from the current schedule, each
    candidate timed as the median of 5 runs after a warm-up.  Drops a captured
    graph.  The choice is stored in the JSON file named by the environment
    variable BSI_TUNE_CACHE (if set) and read back by later plans with the same

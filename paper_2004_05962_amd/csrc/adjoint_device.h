@@ -57,17 +57,25 @@ constexpr int kAdjTiles = 16;                      // tile lanes per row of lane
 // most (kAdjBY - 1)/dy + 2 otherwise): one row of 16 y-tile lanes per column.
 static_assert(kAdjBY <= kAdjTiles, "a brick's y-tiles fit one row of tile lanes");
 
+// The kernels are specialised per x spacing DX = 1..kAdjMaxDX; DX = 0 is the
+// generic kernel for spacings above kAdjMaxDX, and DX = kAdjAnyTile a kernel
+// for any spacing 4..kAdjMaxDX taken at run time (the same operations, in the
+// same order, as the specialisation of that spacing).
+constexpr int kAdjAnyTile = -1;
+
 // Window columns of a brick of kAdjBX voxels at x spacing dx (0: any spacing
-// above kAdjMaxDX): a run of w voxels meets at most (w - 1)/dx + 2 tiles, and
-// exactly w / dx when the run is whole tiles (spacing 1).
+// above kAdjMaxDX; kAdjAnyTile: any of 4..kAdjMaxDX): a run of w voxels meets
+// at most (w - 1)/dx + 2 tiles, and exactly w / dx when the run is whole tiles
+// (spacing 1).
 __host__ __device__ constexpr int adj_cx_max(int dx) {
-  return dx == 1 ? kAdjBX + 3 : (kAdjBX - 1) / (dx > 0 ? dx : kAdjMaxDX + 1) + 5;
+  return dx == 1 ? kAdjBX + 3
+                 : (kAdjBX - 1) / (dx == kAdjAnyTile ? 4 : dx > 0 ? dx : kAdjMaxDX + 1) + 5;
 }
 // The x-contraction runs on tile lanes (16 x-tiles per row of 16 lanes) when a
 // brick row holds at most 16 tiles: x spacing 4 (bricks start on multiples of
 // 64, so exactly 16 tiles), 5..12, and the generic kernel (spacing 13 or more,
 // at most 6 tiles).  Spacings 1..3 sum each column directly (adj_xsum).
-__host__ __device__ constexpr bool adj_tile_lanes(int dx) { return dx == 0 || dx >= 4; }
+__host__ __device__ constexpr bool adj_tile_lanes(int dx) { return dx == 0 || dx == kAdjAnyTile || dx >= 4; }
 
 // Finished partial planes are staged in LDS and stored once per brick.  On
 // this chip loads and stores share one counter of outstanding memory
@@ -91,7 +99,9 @@ constexpr int kAdjYGroup = BSI_ADJ_YGROUP;
 // side at x spacings 4..12, so a tile that reaches past the brick is
 // contracted without a test per voxel: its voxels outside the brick read zero
 // (the voxels of a ragged brick's row past its end are written as zeros too).
-__host__ __device__ constexpr int adj_fpad(int dx) { return dx >= 4 && dx <= kAdjMaxDX ? dx - 1 : 0; }
+__host__ __device__ constexpr int adj_fpad(int dx) {
+  return dx == kAdjAnyTile ? kAdjMaxDX - 1 : dx >= 4 && dx <= kAdjMaxDX ? dx - 1 : 0;
+}
 __host__ __device__ constexpr int adj_frow(int dx) { return kWave + 2 * adj_fpad(dx); }  // row stride (voxels)
 
 template <int DX>
@@ -316,8 +326,13 @@ __device__ __forceinline__ void adj_emit_xf(const AdjBrick& b, AdjSmem<DX>& sm, 
       const float* Fr = adj_frow_ptr<DX>(sm, wave * R + rr);
       if constexpr (adj_fpad(DX) > 0) {
         // voxels xt .. xt + dx - 1 lie in -(dx - 1) .. 63 + dx - 1: no tests
+        if constexpr (DX > 0) {
 #pragma unroll
-        for (int o = 0; o < DX; ++o) adj_moment_step(lut_row(lut, DX, o), ldf3(Fr + (xt + o) * 3), M);
+          for (int o = 0; o < DX; ++o) adj_moment_step(lut_row(lut, DX, o), ldf3(Fr + (xt + o) * 3), M);
+        } else {  // kAdjAnyTile: dx from the geometry, the same operations in the same order
+#pragma unroll 1
+          for (int o = 0; o < dx; ++o) adj_moment_step(lut_row(lut, dx, o), ldf3(Fr + (xt + o) * 3), M);
+        }
       } else {
         const int nxb = b.xe - b.x0;
         auto voxel = [&](int o) {

@@ -40,17 +40,21 @@ struct VolDesc {
   const float* dfield;
   float* grad;
   float* part;
-  int64_t first[3];  // first global work item of this volume: forward, pass 1, pass 2
+  int64_t first[4];  // first global work item of this volume: forward, pass 1 (its class), pass 2,
+                     // pass 1 (spacings 4..12 in one launch)
 };
 
-enum Pass { kFwd = 0, kAdj1 = 1, kAdj2 = 2 };
+enum Pass { kFwd = 0, kAdj1 = 1, kAdj2 = 2, kAdj1Tiles = 3 };
 constexpr int kNumClasses = kAdjMaxDX + 1;  // class dx for dx <= kAdjMaxDX, class 0 otherwise
+constexpr int kTilesLo = 4;                  // classes kTilesLo..kAdjMaxDX: the tile-lane spacings
 inline int dx_class(int dx) { return dx <= kAdjMaxDX ? dx : 0; }
 constexpr int kPtThreads = kGatherThreads;  // pass 2's workgroup
 constexpr int kClassStreams = 3;  // pass-1 class launches run on the caller's stream and these
 
 // ---- schedule knobs: each a small table of values, none changes a result bit
-enum Knob { kKFwdShape, kKFwdItems, kKFwdPerCu, kKAdjPerCu, kKPtsPerCu, kKBranches, kKBeside, kKFwdNT, kNumKnobs };
+enum Knob {
+  kKFwdShape, kKFwdItems, kKFwdPerCu, kKAdjPerCu, kKPtsPerCu, kKBranches, kKBeside, kKFwdNT, kKAdjOne, kNumKnobs
+};
 // forward workgroup shapes R x S (R rows of S 64-voxel strips: FwdTile<R, S, 1>)
 constexpr int kNumFwdShapes = 3;
 static const char* const kFwdShapeName[kNumFwdShapes] = {"4x1", "2x2", "8x1"};
@@ -63,10 +67,11 @@ static const int kPtsPerCu[] = {0, 8};             // pass-2 workgroups per CU (
 static const int kBranches[] = {1, 2, 4};          // streams the pass-1 classes are spread over
 static const int kBeside[] = {1, 0};               // 1: forward beside the adjoint; 0: forward first
 static const int kFwdNT[] = {0, 1};                // forward stores: 0 ordinary, 1 non-temporal
-static const int kKnobSize[kNumKnobs] = {kNumFwdShapes, 3, 4, 4, 2, 3, 2, 2};
+static const int kAdjOne[] = {0, 1};               // 1: spacings 4..12 in one pass-1 launch (run-time spacing)
+static const int kKnobSize[kNumKnobs] = {kNumFwdShapes, 3, 4, 4, 2, 3, 2, 2, 2};
 static const char* const kKnobName[kNumKnobs] = {"fwd_tile",      "fwd_items",     "fwd_wg_per_cu",
                                                  "adj_wg_per_cu", "pts_wg_per_cu", "pass1_streams",
-                                                 "fwd_beside",    "fwd_nt_stores"};
+                                                 "fwd_beside",    "fwd_nt_stores", "pass1_one_launch"};
 static_assert(kClassStreams + 1 >= 4, "the largest pass1_streams value");
 
 struct BatchConfig {
@@ -75,7 +80,7 @@ struct BatchConfig {
 // The starting point of the search: 4x1 forward, 2048 items per volume, one
 // workgroup per item in every pass, pass 1 over 4 streams, forward beside the
 // adjoint with ordinary stores.
-static const BatchConfig kDefaultConfig = {{0, 1, 0, 0, 0, 2, 0, 0}};
+static const BatchConfig kDefaultConfig = {{0, 1, 0, 0, 0, 2, 0, 0, 0}};
 
 int config_count() {
   int n = 1;
@@ -109,7 +114,8 @@ std::string describe_config(const BatchConfig& c) {
       case kKPtsPerCu: out += std::to_string(kPtsPerCu[c.k[i]]); break;
       case kKBranches: out += std::to_string(kBranches[c.k[i]]); break;
       case kKBeside: out += std::to_string(kBeside[c.k[i]]); break;
-      default: out += std::to_string(kFwdNT[c.k[i]]); break;
+      case kKFwdNT: out += std::to_string(kFwdNT[c.k[i]]); break;
+      default: out += std::to_string(kAdjOne[c.k[i]]); break;
     }
   }
   return out;
@@ -155,17 +161,20 @@ __global__ __launch_bounds__(T::threads) void batch_fwd_kernel(const VolDesc* __
 // Pass 1 over the volumes of one x-spacing class (DX = 1..kAdjMaxDX, or 0 for
 // the generic path), each class with its own descriptor sub-table, so every
 // launch keeps the register footprint of its own specialisation.
+// (DX = kAdjAnyTile: the volumes of every spacing 4..12, item numbering
+// first[kAdj1Tiles]; the same bits as each spacing's own kernel.)
 template <int DX, bool Persistent>
 __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(BSI_ADJ_WPE))) void batch_adj1_kernel(
     const VolDesc* __restrict__ vols, int count, int64_t total, const float* __restrict__ lut) {
   __shared__ AdjSmem<DX> sm;
+  constexpr int kPass = DX == kAdjAnyTile ? kAdj1Tiles : kAdj1;
   BSI_BATCH_ITEMS(item, total, Persistent) {
-    const int vi = uniform(find_volume(vols, count, item, kAdj1));
+    const int vi = uniform(find_volume(vols, count, item, kPass));
     const VolDesc& d = vols[vi];
     const AdjGeom a = d.a;
     // ordinary loads: with the forward running beside pass 1 in the graph,
     // streaming loads measured 2-5% slower here
-    const int brick = (int)(item - d.first[kAdj1]);
+    const int brick = (int)(item - d.first[kPass]);
     if (adj_stage_all(a))
       adj_brick<DX, false, true>(as_global(d.dfield), as_global(d.part), a, lut, brick, sm, threadIdx.x);
     else
@@ -201,6 +210,7 @@ struct bsi_batch {
   std::vector<VolDesc> cls_host;
   int cls_first[kNumClasses + 1] = {};  // class c holds cls_host[cls_first[c] .. cls_first[c+1])
   int64_t cls_total[kNumClasses] = {};
+  int64_t tiles_total = 0;  // pass-1 items of classes kTilesLo.. (first[kAdj1Tiles] numbering)
   VolDesc* d_cls = nullptr;
   float* d_part = nullptr;
   const float* lut = nullptr;
@@ -336,18 +346,37 @@ hipError_t launch_adj1_class(bsi_batch* p, int c, hipStream_t s) {
 // into `s` before pass 2.
 int32_t enqueue_adjoint(bsi_batch* p, hipStream_t s) {
   hipError_t e;
-  int order[kNumClasses];
+  // launches: one per class, or (pass1_one_launch) classes kTilesLo.. as one
+  // launch (index kNumClasses) and the others on their own
+  const bool one = kAdjOne[p->cfg.k[kKAdjOne]] != 0;
+  int64_t size[kNumClasses + 1] = {};
+  int order[kNumClasses + 1];
   int used = 0;
   for (int c = 0; c < kNumClasses; ++c)
-    if (p->cls_total[c] > 0) order[used++] = c;
-  std::stable_sort(order, order + used, [p](int a, int b) { return p->cls_total[a] > p->cls_total[b]; });
+    if (p->cls_total[c] > 0 && !(one && c >= kTilesLo)) {
+      size[c] = p->cls_total[c];
+      order[used++] = c;
+    }
+  if (one && p->tiles_total > 0) {
+    size[kNumClasses] = p->tiles_total;
+    order[used++] = kNumClasses;
+  }
+  std::stable_sort(order, order + used, [&size](int a, int b) { return size[a] > size[b]; });
   const int branches = std::min(used, kBranches[p->cfg.k[kKBranches]]);
   for (int j = 0; j + 1 < branches; ++j)
     if ((e = hipStreamWaitEvent(p->cls_side[j], p->fork, 0)) != hipSuccess) return hip_fail(e, "forking pass 1");
   for (int k = 0; k < used; ++k) {
     const int b = k % branches;
     hipStream_t st = b == 0 ? s : p->cls_side[b - 1];
-    if ((e = launch_adj1_class(p, order[k], st)) != hipSuccess) return hip_fail(e, "launching batched adjoint pass 1");
+    if (order[k] == kNumClasses) {
+      const int n = p->cls_first[kNumClasses] - p->cls_first[kTilesLo];
+      launch_adj1_dx<kAdjAnyTile>(p, p->d_cls + p->cls_first[kTilesLo], n, p->tiles_total,
+                                  kAdjPerCu[p->cfg.k[kKAdjPerCu]], st);
+      e = hipGetLastError();
+    } else {
+      e = launch_adj1_class(p, order[k], st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "launching batched adjoint pass 1");
   }
   for (int j = 0; j + 1 < branches; ++j) {
     if ((e = hipEventRecord(p->cls_join[j], p->cls_side[j])) != hipSuccess) return hip_fail(e, "recording a pass-1 join");
@@ -511,8 +540,8 @@ std::string plan_key(const bsi_batch* p) {
     mix(d.a.g.dx); mix(d.a.g.dy); mix(d.a.g.dz);
   }
   char buf[64];
-  // "k2": the knob tables of this version (an index means another schedule under other tables)
-  std::snprintf(buf, sizeof(buf), "k2-gfx950-cu%d-%016llx", p->cus, (unsigned long long)h);
+  // "k3": the knob tables of this version (an index means another schedule under other tables)
+  std::snprintf(buf, sizeof(buf), "k3-gfx950-cu%d-%016llx", p->cus, (unsigned long long)h);
   return buf;
 }
 
@@ -593,6 +622,11 @@ int32_t bsi_batch_create(int32_t count, const int32_t* dims3xN, const int32_t* s
     }
   }
   p->cls_first[kNumClasses] = (int)p->cls_host.size();
+  for (int i = p->cls_first[kTilesLo]; i < p->cls_first[kNumClasses]; ++i) {  // class order
+    VolDesc& d = p->cls_host[(size_t)i];
+    d.first[kAdj1Tiles] = p->tiles_total;
+    p->tiles_total += (int64_t)d.a.x.nb * d.a.y.nb * d.a.z.nb;
+  }
 
   if (hipMalloc(&p->d_cls, sizeof(VolDesc) * (size_t)count) != hipSuccess) {
     (void)hipGetLastError();

@@ -41,6 +41,14 @@ bool check_adj_brick(const AdjGeom& a, const AdjBrick& b, Check& ck) {
   REQUIRE(b.Cx <= adj_cx_max(dxc), "x window within the H buffer's row");
   REQUIRE(b.Cy - 3 <= kAdjTiles, "y-tiles within one row of tile lanes");
   if (adj_tile_lanes(dxc)) REQUIRE(b.ntx <= kAdjTiles, "x-tiles within one row of tile lanes");
+  if (a.g.dx >= 4 && a.g.dx <= kAdjMaxDX) {  // the run-time-spacing kernel (batched pass 1) reads the same bricks
+    REQUIRE(b.Cx <= adj_cx_max(kAdjAnyTile), "x window within the run-time-spacing kernel's H row");
+    for (int t = 0; t < b.ntx; ++t) {
+      const int xt = (b.cx0 + t) * a.g.dx - b.x0;
+      REQUIRE(xt >= -adj_fpad(kAdjAnyTile) && xt + a.g.dx <= kWave + adj_fpad(kAdjAnyTile),
+              "x-tile within the run-time-spacing kernel's padded F row");
+    }
+  }
   if (adj_fpad(dxc) > 0)  // a tile's voxels, read without tests, lie within the row and its zero pads
     for (int t = 0; t < b.ntx; ++t) {
       const int xt = (b.cx0 + t) * a.g.dx - b.x0;

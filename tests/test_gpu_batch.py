@@ -72,7 +72,7 @@ def test_batched_equals_per_volume_bits(batch):
     plan.bind(grids, f, dfields, g)
     schedules, universe = _covering_schedules(plan)
     say("batch: schedules", schedules, "cover", len(universe), "knob values")
-    assert len(universe) == 3 + 3 + 4 + 4 + 2 + 3 + 2 + 2
+    assert len(universe) == 3 + 3 + 4 + 4 + 2 + 3 + 2 + 2 + 2
     for sched in schedules:
         _force(plan, sched)
         for t in f + g:
