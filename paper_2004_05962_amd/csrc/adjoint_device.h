@@ -11,7 +11,7 @@
 // brick's voxel rows and is contracted in LDS:
 //   over x, per wave (its own rows), on tile lanes: lane (row, t) forms the
 //     x-moments of tile t, M_l = sum_o Bx_l(o) A0[row][t dx + o], and the 16
-//     lanes of a row combine them with row rotations (DPP):
+//     lanes of a row combine them with row shifts (DPP):
 //     H[row][cx] = sum_l M_l(tile cx - l);
 //   then, after one workgroup barrier, over y, the same way on y-tile lanes:
 //     G[cy][cx] = sum_m N_m(tile cy - m),  N_m = sum_oy By_m(oy) H[t dy + oy][cx].
@@ -189,38 +189,50 @@ __device__ __forceinline__ void adj_zero_fpad(AdjSmem<DX>& sm, int wave, int lan
   }
 }
 
-// Value of lane (i - N) mod 16 of this lane's row of 16 lanes (DPP row_ror).
+// Value of lane i - N of this lane's row of 16 lanes, 0 for i < N (DPP
+// row_shr); row_shl: lane i + N, 0 for i + N >= 16.  Lanes past the row's
+// edge read the zero `old` operand.
 template <int N>
-__device__ __forceinline__ float row_ror(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x120 + N, 0xF, 0xF, false));
+__device__ __forceinline__ float row_shr(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x110 + N, 0xF, 0xF, true));
 }
-
-template <int L>
-__device__ __forceinline__ void adj_combine_term(int t, const F3& m, F3& cm, F3& cw) {
-  const F3 r{row_ror<L>(m.x), row_ror<L>(m.y), row_ror<L>(m.z)};  // M_L of tile t - L (mod 16)
-  if (t >= L) {
-    cm.x += r.x;
-    cm.y += r.y;
-    cm.z += r.z;
-  } else {
-    cw.x += r.x;
-    cw.y += r.y;
-    cw.z += r.z;
-  }
+template <int N>
+__device__ __forceinline__ float row_shl(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x100 + N, 0xF, 0xF, true));
 }
 
 // Window column of tile lanes: lane t of a row of 16 holds the moments M_l of
 // tile t; this forms
 //   cm = S[t]      = sum_{l <= t} M_l(tile t - l)
 //   cw = S[16 + t] = sum_{l > t}  M_l(tile 16 + t - l)   (t < 3)
-// l ascending.  Idle lanes hold M = 0, so columns past the last tile come out
-// right.  Every lane of the wave takes part (no lane may be inactive).
-__device__ __forceinline__ void adj_combine(int t, const F3 (&M)[4], F3& cm, F3& cw) {
+// l ascending.  The shifts bring in zero for the terms a lane does not take
+// (row_shr by l for l > t, row_shl by 16 - l for l <= t), and adding zero is
+// exact, so no per-lane selects are needed.  Idle lanes hold M = 0, so columns
+// past the last tile come out right.  Every lane of the wave takes part (no
+// lane may be inactive).
+__device__ __forceinline__ void adj_combine(const F3 (&M)[4], F3& cm, F3& cw) {
   cm = M[0];
-  cw = F3{0.f, 0.f, 0.f};
-  adj_combine_term<1>(t, M[1], cm, cw);
-  adj_combine_term<2>(t, M[2], cm, cw);
-  adj_combine_term<3>(t, M[3], cm, cw);
+  cm.x += row_shr<1>(M[1].x);
+  cm.y += row_shr<1>(M[1].y);
+  cm.z += row_shr<1>(M[1].z);
+  cm.x += row_shr<2>(M[2].x);
+  cm.y += row_shr<2>(M[2].y);
+  cm.z += row_shr<2>(M[2].z);
+  cm.x += row_shr<3>(M[3].x);
+  cm.y += row_shr<3>(M[3].y);
+  cm.z += row_shr<3>(M[3].z);
+  cw.x = row_shl<15>(M[1].x);
+  cw.y = row_shl<15>(M[1].y);
+  cw.z = row_shl<15>(M[1].z);
+  cw.x += row_shl<14>(M[2].x);
+  cw.y += row_shl<14>(M[2].y);
+  cw.z += row_shl<14>(M[2].z);
+  cw.x += row_shl<13>(M[3].x);
+  cw.y += row_shl<13>(M[3].y);
+  cw.z += row_shl<13>(M[3].z);
+  // cm is formed here, not sunk into the callers' conditional stores (which
+  // keeps all nine shifted values live at once and spills)
+  asm volatile("" : "+v"(cm.x), "+v"(cm.y), "+v"(cm.z));
 }
 
 // Moments += w_l * v for l = 0..3.
@@ -349,7 +361,7 @@ __device__ __forceinline__ void adj_emit_xf(const AdjBrick& b, AdjSmem<DX>& sm, 
       }
     }
     F3 cm, cw;
-    adj_combine(t, M, cm, cw);  // every lane of the wave takes part
+    adj_combine(M, cm, cw);  // every lane of the wave takes part
     if (rr < R && rr < nrow) {
       float* hrow = H + (wave * R + rr) * CXM * 3;
       if (t < b.Cx) stf3(hrow + t * 3, cm);
@@ -409,7 +421,7 @@ __device__ __forceinline__ void adj_emit_y(const AdjGeom& a, const AdjBrick& b, 
         if (oy0 + j < g.dy) adj_moment_step(lut_row(lut, g.dy, oy0 + j), v[j], N);
     }
     F3 gm, gw;
-    adj_combine(ty, N, gm, gw);  // every lane of the wave takes part
+    adj_combine(N, gm, gw);  // every lane of the wave takes part
     if (cxl < b.Cx) {
       float* dst = StageAll ? sm.P : pbase;
       if (ty < b.Cy) stf3(dst + adj_part_offset(a, czl, ty, cxl), gm);
@@ -469,25 +481,25 @@ __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, floa
   int oz = 0;  // offset within the tile
   const float* ahead = plane0 + 2 * zs;  // the plane two ahead of the next one
 
-// Control plane CZL, in slot PH (uniform), goes to this wave's rows of F (the
-// selects read every slot; each slot is cleared by its own select), then the
-// shared emission.
+// Control plane CZL, in slot PH (uniform), goes to this wave's rows of F and
+// the slot is cleared, then the shared emission.
+// A scalar branch to the slot's own code: constant register indices, no selects.
+#define BSI_ADJ_PUT_SLOT(K)                                                                \
+  _Pragma("unroll") for (int r = 0; r < R; ++r) {                                        \
+    adj_put_f<DX, R>(sm, b, wave, lane, r, acc[K][r]);                                   \
+    acc[K][r] = F3{0.f, 0.f, 0.f};                                                       \
+  }
+#define BSI_ADJ_PUT(PH)                                                                    \
+  switch (PH) {                                                                          \
+    case 0: BSI_ADJ_PUT_SLOT(0) break;                                                   \
+    case 1: BSI_ADJ_PUT_SLOT(1) break;                                                   \
+    case 2: BSI_ADJ_PUT_SLOT(2) break;                                                   \
+    default: BSI_ADJ_PUT_SLOT(3) break;                                                  \
+  }
 #define BSI_ADJ_EMIT(CZL, PH, LAST)                                                        \
   {                                                                                      \
-    const int ph_ = (PH);                                                                \
     wave_lds_sync(); /* this wave's x-contraction of the previous plane is done with F */ \
-    _Pragma("unroll") for (int r = 0; r < R; ++r) {                                      \
-      F3 v;                                                                              \
-      v.x = ph_ == 0 ? acc[0][r].x : ph_ == 1 ? acc[1][r].x : ph_ == 2 ? acc[2][r].x : acc[3][r].x; \
-      v.y = ph_ == 0 ? acc[0][r].y : ph_ == 1 ? acc[1][r].y : ph_ == 2 ? acc[2][r].y : acc[3][r].y; \
-      v.z = ph_ == 0 ? acc[0][r].z : ph_ == 1 ? acc[1][r].z : ph_ == 2 ? acc[2][r].z : acc[3][r].z; \
-      adj_put_f<DX, R>(sm, b, wave, lane, r, v);                                         \
-      _Pragma("unroll") for (int k = 0; k < 4; ++k) {                                    \
-        acc[k][r].x = k == ph_ ? 0.f : acc[k][r].x;                                      \
-        acc[k][r].y = k == ph_ ? 0.f : acc[k][r].y;                                      \
-        acc[k][r].z = k == ph_ ? 0.f : acc[k][r].z;                                      \
-      }                                                                                  \
-    }                                                                                    \
+    BSI_ADJ_PUT(PH)                                                                      \
     wave_lds_sync();                                                                     \
     adj_emit_xf<DX, R>(b, sm, lut, dx, tid, (CZL));                                      \
     __syncthreads();                                                                     \
@@ -543,6 +555,8 @@ __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, floa
   for (int n = 0; n < 4; ++n) BSI_ADJ_EMIT(t + n, (t + n) & 3, n == 3)
 #undef BSI_ADJ_PLANE
 #undef BSI_ADJ_EMIT
+#undef BSI_ADJ_PUT
+#undef BSI_ADJ_PUT_SLOT
 }
 
 // Pass 2 for one control point (cx, cy, cz): fixed-order sum of brick partials.

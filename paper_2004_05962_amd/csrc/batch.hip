@@ -131,17 +131,26 @@ __device__ __forceinline__ int find_volume(const VolDesc* __restrict__ v, int co
   return lo;
 }
 
-// The items of this workgroup (batch_items).
-#define BSI_BATCH_ITEMS(item, total, Persistent)                                            \
-  for (ItemRange r_ = batch_items(blockIdx.x, gridDim.x, (total), (Persistent)); r_.first < (total); \
-       r_.first += r_.step)                                                                \
-    if (const int64_t item = r_.first; true)
+// body(item) for each item of this workgroup (batch_items): a loop over a
+// persistent grid; otherwise one test and one call, so that no loop state stays
+// live across the body (pass 1's body needs every scalar register it can get:
+// with a loop around it, its scalar registers spill to vector registers and
+// those to scratch).
+template <bool Persistent, class Body>
+__device__ __forceinline__ void batch_for_items(int64_t total, Body&& body) {
+  const ItemRange r = batch_items(blockIdx.x, gridDim.x, total, Persistent);
+  if constexpr (Persistent) {
+    for (int64_t item = r.first; item < total; item += r.step) body(item);
+  } else {
+    if (r.first < total) body(r.first);
+  }
+}
 
 template <class T, bool NT, bool Persistent>
 __global__ __launch_bounds__(T::threads) void batch_fwd_kernel(const VolDesc* __restrict__ vols, int count,
                                                                int64_t total, const float* __restrict__ lut) {
   __shared__ FwdSmem<3, T> sm;
-  BSI_BATCH_ITEMS(item, total, Persistent) {
+  batch_for_items<Persistent>(total, [&](const int64_t item) {
     const int vi = uniform(find_volume(vols, count, item, kFwd));
     const VolDesc& d = vols[vi];
     const VolGeom g = d.a.g;
@@ -155,7 +164,7 @@ __global__ __launch_bounds__(T::threads) void batch_fwd_kernel(const VolDesc* __
     const int z1 = min(g.nz, z0 + L.zchunk);
     fwd_block<3, T, NT, !NT>(as_global(d.grid), as_global(d.field), g, lut, bx * T::width, by * T::rows, z0, z1, sm,
                              threadIdx.x);
-  }
+  });
 }
 
 // Pass 1 over the volumes of one x-spacing class (DX = 1..kAdjMaxDX, or 0 for
@@ -168,7 +177,7 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(BSI
     const VolDesc* __restrict__ vols, int count, int64_t total, const float* __restrict__ lut) {
   __shared__ AdjSmem<DX> sm;
   constexpr int kPass = DX == kAdjAnyTile ? kAdj1Tiles : kAdj1;
-  BSI_BATCH_ITEMS(item, total, Persistent) {
+  batch_for_items<Persistent>(total, [&](const int64_t item) {
     const int vi = uniform(find_volume(vols, count, item, kPass));
     const VolDesc& d = vols[vi];
     const AdjGeom a = d.a;
@@ -179,18 +188,18 @@ __global__ __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(BSI
       adj_brick<DX, false, true>(as_global(d.dfield), as_global(d.part), a, lut, brick, sm, threadIdx.x);
     else
       adj_brick<DX, false, false>(as_global(d.dfield), as_global(d.part), a, lut, brick, sm, threadIdx.x);
-  }
+  });
 }
 
 template <bool Persistent>
 __global__ __launch_bounds__(kPtThreads) void batch_adj2_kernel(const VolDesc* __restrict__ vols, int count,
                                                                  int64_t total) {
-  BSI_BATCH_ITEMS(item, total, Persistent) {
+  batch_for_items<Persistent>(total, [&](const int64_t item) {
     const int vi = uniform(find_volume(vols, count, item, kAdj2));
     const VolDesc& d = vols[vi];
     const AdjGeom a = d.a;
     adj_gather_block(as_global(d.part), as_global(d.grad), a, (int)(item - d.first[kAdj2]), threadIdx.x);
-  }
+  });
 }
 
 }  // namespace bsi

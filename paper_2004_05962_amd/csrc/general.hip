@@ -253,7 +253,7 @@ __global__ __launch_bounds__(kGzThreads) __attribute__((amdgpu_waves_per_eu(6)))
     // x.  Tile lanes when the brick meets at most 16 x-tiles (as in the aligned
     // pass 1): lane (rr, t) of this wave forms the 4 moments of tile cx0 + t
     // of its row rr, M_l = sum over the tile's voxels (ascending) of
-    // B_l(u(v)) F[v], and DPP row rotations combine them into the window
+    // B_l(u(v)) F[v], and DPP row shifts combine them into the window
     // columns, H[j] = sum_l M_l(tile j - l).  Otherwise one lane per (row,
     // column), summing the column's voxels tile by tile.
     if constexpr (XTiles) {
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kGzThreads) __attribute__((amdgpu_waves_per_eu(6)))
         for (int v = va; v < vb; ++v) adj_moment_step(wxT + 4 * v, ldf3(Fr + 3 * v), M);
       }
       F3 cm, cw;
-      adj_combine(tt, M, cm, cw);  // every lane of the wave takes part
+      adj_combine(M, cm, cw);  // every lane of the wave takes part
       if (rowok) {
         float* hrow = H + row * a.cmx * 3;
         if (tt < b.Cx) stf3(hrow + tt * 3, cm);
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(kGzThreads) __attribute__((amdgpu_waves_per_eu(6)))
     // y, on y-tile lanes (a brick of 16 rows meets at most 16 y-tiles): lane
     // (c4, ty) of wave w takes window column 4 w + c4 (then + 32 ...) and
     // y-tile cy0 + ty, forms N_m = sum over the tile's rows (ascending) of
-    // B_m(v(y)) H[y][column], and the rotations give window rows ty and
+    // B_m(v(y)) H[y][column], and the shifts give window rows ty and
     // (ty < 3) 16 + ty.
     {
       const int c4 = lane / kAdjTiles, ty = lane % kAdjTiles;
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(kGzThreads) __attribute__((amdgpu_waves_per_eu(6)))
           for (int y = ya; y < yb; ++y) adj_moment_step(wyT + 4 * y, ldf3(H + (y * a.cmx + j) * 3), N);
         }
         F3 gm, gw;
-        adj_combine(ty, N, gm, gw);  // every lane of the wave takes part
+        adj_combine(N, gm, gw);  // every lane of the wave takes part
         if (j < b.Cx) {
           if (ty < b.Cy) stf3(P + ((size_t)(czl * a.cmy + ty) * a.cmx + j) * 3, gm);
           if (ty < 3 && kAdjTiles + ty < b.Cy) stf3(P + ((size_t)(czl * a.cmy + kAdjTiles + ty) * a.cmx + j) * 3, gw);
