@@ -77,10 +77,12 @@ static_assert(kClassStreams + 1 >= 4, "the largest pass1_streams value");
 struct BatchConfig {
   int k[kNumKnobs];  // value index of each knob
 };
-// The starting point of the search: 4x1 forward, 2048 items per volume, one
-// workgroup per item in every pass, pass 1 over 4 streams, forward beside the
-// adjoint with ordinary stores.
-static const BatchConfig kDefaultConfig = {{0, 1, 0, 0, 0, 2, 0, 0, 0}};
+// The starting point of the search: 8x1 forward, 512 items per volume, one
+// workgroup per item in every pass, pass 1 in one launch for the spacings
+// 4..12 and per class for the rest over 4 streams, forward first with
+// ordinary stores (among the fastest graphs measured on the 32-volume
+// workload).
+static const BatchConfig kDefaultConfig = {{2, 0, 0, 0, 0, 2, 1, 0, 1}};
 
 int config_count() {
   int n = 1;
@@ -786,30 +788,38 @@ int32_t bsi_batch_tune(bsi_batch* p, hipStream_t stream) {
     return set_config(p, decode_config(v));
   }
   hipEvent_t t0, t1;
+  hipStream_t cap;
   hipError_t e;
   if ((e = hipEventCreate(&t0)) != hipSuccess) return hip_fail(e, "creating a timing event");
   if ((e = hipEventCreate(&t1)) != hipSuccess) {
     (void)hipEventDestroy(t0);
     return hip_fail(e, "creating a timing event");
   }
+  if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) {
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    return hip_fail(e, "creating the capture stream");
+  }
   const bool verbose = std::getenv("BSI_TUNE_VERBOSE") != nullptr;
-  // Median of 5 timed runs after one warm-up run.  Every run ends with the
-  // wait for t1 on `stream`, into which all of the plan's branches join, so
-  // the device is idle whenever set_config rewrites the forward's table.
+  // Each candidate is timed the way the plan runs in the end: captured into a
+  // graph (on a stream of the tuner's own, since `stream` may be the null
+  // stream, which cannot capture) and replayed on `stream`.  Median of 7
+  // replays after one warm-up replay; each replay is waited for, so the device
+  // is idle whenever set_config rewrites the forward's table.
   auto time_config = [&](const BatchConfig& c, float* ms) -> int32_t {
     int32_t r = set_config(p, c);
     if (r) return r;
-    if ((r = enqueue(p, stream))) return r;
-    float times[5];
-    for (int k = 0; k < 5; ++k) {
-      if ((e = hipEventRecord(t0, stream)) != hipSuccess) return hip_fail(e, "recording a timing event");
-      if ((r = enqueue(p, stream))) return r;
-      if ((e = hipEventRecord(t1, stream)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess ||
+    if ((r = build_graph(p, cap))) return r;
+    if ((e = hipGraphLaunch(p->exec, stream)) != hipSuccess) return hip_fail(e, "launching a tuning graph");
+    float times[7];
+    for (int k = 0; k < 7; ++k) {
+      if ((e = hipEventRecord(t0, stream)) != hipSuccess || (e = hipGraphLaunch(p->exec, stream)) != hipSuccess ||
+          (e = hipEventRecord(t1, stream)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess ||
           (e = hipEventElapsedTime(&times[k], t0, t1)) != hipSuccess)
         return hip_fail(e, "timing a configuration");
     }
-    std::sort(times, times + 5);
-    *ms = times[2];
+    std::sort(times, times + 7);
+    *ms = times[3];
     if (verbose) std::fprintf(stderr, "bsi_batch_tune: %-110s %.4f ms\n", describe_config(c).c_str(), *ms);
     return BSI_OK;
   };
@@ -855,9 +865,12 @@ int32_t bsi_batch_tune(bsi_batch* p, hipStream_t stream) {
     if ((rc = time_config(best, &again)) == BSI_OK && (rc = time_config(start, &base)) == BSI_OK && base <= again)
       best = start;
   }
+  if (rc != BSI_OK) (void)hipDeviceSynchronize();  // a failed candidate may have left work behind
+  else if ((e = hipStreamSynchronize(stream)) != hipSuccess) rc = hip_fail(e, "finishing the tuning runs");
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
-  const int32_t rc2 = set_config(p, rc == BSI_OK ? best : start);
+  (void)hipStreamDestroy(cap);
+  const int32_t rc2 = set_config(p, rc == BSI_OK ? best : start);  // drops the last tuning graph
   if (rc == BSI_OK) rc = rc2;
   if (rc == BSI_OK)
     if (const char* path = std::getenv("BSI_TUNE_CACHE")) cache_store(path, p->key, encode_config(p->cfg));
