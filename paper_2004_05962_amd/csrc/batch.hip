@@ -60,7 +60,10 @@ constexpr int kNumFwdShapes = 3;
 static const char* const kFwdShapeName[kNumFwdShapes] = {"4x1", "2x2", "8x1"};
 static const int kFwdShapeWidth[kNumFwdShapes] = {64, 128, 64};
 static const int kFwdShapeRows[kNumFwdShapes] = {4, 2, 8};
-static const int kFwdItems[] = {512, 2048, 8192};  // forward items per volume (the z split aims at this)
+#ifndef BSI_FWD_ITEMS_LIST
+#define BSI_FWD_ITEMS_LIST 512, 2048, 8192
+#endif
+static const int kFwdItems[] = {BSI_FWD_ITEMS_LIST};  // forward items per volume (the z split aims at this)
 static const int kFwdPerCu[] = {0, 2, 4, 8};       // forward workgroups per CU (0: one per item)
 static const int kAdjPerCu[] = {0, 1, 2, 3};       // pass-1 workgroups per CU (0: one per brick)
 static const int kPtsPerCu[] = {0, 8};             // pass-2 workgroups per CU (0: one per block)

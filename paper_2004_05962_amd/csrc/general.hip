@@ -161,7 +161,9 @@ struct GenTables3 {
 // Thread k of an axis's workgroups writes entry k of its tables: tile[k] =
 // i(k) and w[k] = B(u(k)) for k < n, and first[k] = min{v : i(v) >= k} for
 // k <= g (first[g] = n), found by bisection on the exact i(v), so the three
-// tables need no order between them.
+// tables need no order between them.  The z weights are stored in pass 1's
+// accumulator order: entry s of voxel k is the weight of control plane c with
+// c mod 4 = s, i.e. B_{(s - i(k)) mod 4}.
 __global__ __launch_bounds__(256) void gen_tables3_kernel(GenTables3 p) {
   int blk = blockIdx.x, i = 0;
   while (i < 2 && blk >= p.nb[i]) blk -= p.nb[i++];
@@ -169,9 +171,11 @@ __global__ __launch_bounds__(256) void gen_tables3_kernel(GenTables3 p) {
   const int k = blk * 256 + threadIdx.x;
   if (k < a.n) {
     float b[4];
-    p.tile[i][k] = gen_weights(a, k, b);
+    const int tk = gen_weights(a, k, b);
+    p.tile[i][k] = tk;
+    const int rot = i == 2 ? tk & 3 : 0;
 #pragma unroll
-    for (int l = 0; l < 4; ++l) p.w[i][4 * k + l] = b[l];
+    for (int s = 0; s < 4; ++s) p.w[i][4 * k + s] = b[(s - rot) & 3];
   }
   if (k <= a.g) {
     int lo = 0, hi = a.n;  // i(v) is nondecreasing in v
@@ -191,7 +195,7 @@ __global__ __launch_bounds__(256) void gen_tables3_kernel(GenTables3 p) {
 // z-tiles, [first_z[b kz], first_z[(b+1) kz]).  Per voxel plane a lane adds
 // its 2 voxels into the 4 control planes they meet, with the plane's z
 // weights (scalar loads of the z table); slot k of the accumulators holds
-// control plane c with (c - cz0) mod 4 = k.  When the plane's z-tile ends,
+// control plane c with c mod 4 = k.  When the plane's z-tile ends,
 // control plane t is finished and is contracted in LDS: over x, output
 // column c of a row sums the brick's voxels v in [first_x[c-3], first_x[c+1])
 // (ascending) with weight B_{c - i(v)}(u(v)); then, after a workgroup barrier,
@@ -200,8 +204,12 @@ __global__ __launch_bounds__(256) void gen_tables3_kernel(GenTables3 p) {
 // fixed order.  No atomics.
 // XTiles: every brick meets at most 16 x-tiles (window width cmx <= 19), so
 // the x-contraction runs on tile lanes.
+// Waves per SIMD pass 1 is compiled for (a register bound of 512 / this).
+#ifndef BSI_GZ_WPE
+#define BSI_GZ_WPE 6
+#endif
 template <bool XTiles>
-__global__ __launch_bounds__(kGzThreads) __attribute__((amdgpu_waves_per_eu(6))) void gen_zf_pass1_kernel(const float* __restrict__ dfield,
+__global__ __launch_bounds__(kGzThreads) __attribute__((amdgpu_waves_per_eu(BSI_GZ_WPE))) void gen_zf_pass1_kernel(const float* __restrict__ dfield,
                                                                    float* __restrict__ part, GenGeom q, GenAdj a,
                                                                    GzTables T) {
   extern __shared__ float gz_smem[];
@@ -246,8 +254,8 @@ __global__ __launch_bounds__(kGzThreads) __attribute__((amdgpu_waves_per_eu(6)))
 #pragma unroll
     for (int r = 0; r < kGzRows; ++r) acc[k][r] = F3{0.f, 0.f, 0.f};
 
-  // control plane CZL (slot PH, uniform): this wave's rows go to F, the slot is
-  // cleared, then the x- and y-contractions into the partials
+  // the x- and y-contractions of brick-relative control plane czl, whose
+  // rows the waves have put in F, into the partials
   auto contract = [&](int czl, bool last) {
     float* H = gz_smem + L.H + (czl & 1) * kGzBY * a.cmx * 3;
     // x.  Tile lanes when the brick meets at most 16 x-tiles (as in the aligned
@@ -333,40 +341,37 @@ __global__ __launch_bounds__(kGzThreads) __attribute__((amdgpu_waves_per_eu(6)))
     }
   };
 
+// Slot K (a constant) goes to this wave's rows of F and is cleared.
+#define BSI_GZ_PUT_SLOT(K)                                                                    \
+  _Pragma("unroll") for (int r = 0; r < kGzRows; ++r) {                                       \
+    stf3(F + ((wave * kGzRows + r) * kGzBX + lane) * 3, acc[K][r]);                           \
+    acc[K][r] = F3{0.f, 0.f, 0.f};                                                            \
+  }
+// Control plane CZL (brick-relative), held in slot PH (uniform): its rows go
+// to F by a scalar branch to that slot's own code, then the x- and
+// y-contractions into the partials.
 #define BSI_GZ_EMIT(CZL, PH, LAST)                                                              \
   {                                                                                           \
-    const int ph_ = (PH);                                                                     \
     wave_lds_sync(); /* this wave's x-contraction of the previous plane is done with F */      \
-    _Pragma("unroll") for (int r = 0; r < kGzRows; ++r) {                                     \
-      F3 v;                                                                                   \
-      v.x = ph_ == 0 ? acc[0][r].x : ph_ == 1 ? acc[1][r].x : ph_ == 2 ? acc[2][r].x : acc[3][r].x; \
-      v.y = ph_ == 0 ? acc[0][r].y : ph_ == 1 ? acc[1][r].y : ph_ == 2 ? acc[2][r].y : acc[3][r].y; \
-      v.z = ph_ == 0 ? acc[0][r].z : ph_ == 1 ? acc[1][r].z : ph_ == 2 ? acc[2][r].z : acc[3][r].z; \
-      stf3(F + ((wave * kGzRows + r) * kGzBX + lane) * 3, v);                                 \
-      _Pragma("unroll") for (int k = 0; k < 4; ++k) {                                         \
-        acc[k][r].x = k == ph_ ? 0.f : acc[k][r].x;                                           \
-        acc[k][r].y = k == ph_ ? 0.f : acc[k][r].y;                                           \
-        acc[k][r].z = k == ph_ ? 0.f : acc[k][r].z;                                           \
-      }                                                                                       \
+    switch (PH) {                                                                             \
+      case 0: BSI_GZ_PUT_SLOT(0) break;                                                       \
+      case 1: BSI_GZ_PUT_SLOT(1) break;                                                       \
+      case 2: BSI_GZ_PUT_SLOT(2) break;                                                       \
+      default: BSI_GZ_PUT_SLOT(3) break;                                                      \
     }                                                                                         \
     wave_lds_sync();                                                                          \
     contract((CZL), (LAST));                                                                  \
   }
 
-// One voxel plane Z from register set D: the z-accumulation with the plane's
-// weights (slot k takes B_{(k - ph) mod 4}, ph = (t - cz0) mod 4 for the
-// plane's z-tile t), the loads of the plane two ahead into the same registers
-// (when LOAD), then, when Z is the last plane of tile t (tend = first_z[t+1]),
-// the contraction of control plane t; s >= 1, so the next tile is t + 1.
+// One voxel plane Z from register set D: the z-accumulation (slot k holds
+// control plane c with c mod 4 = k, and the table holds the plane's weights
+// in that order: one scalar load), the loads of the plane two ahead into the
+// same registers (when LOAD), then, when Z is the last plane of tile t
+// (tend = first_z[t+1]), the contraction of control plane t, in slot t mod 4;
+// s >= 1, so the next tile is t + 1.
 #define BSI_GZ_PLANE(D, Z, LOAD)                                                              \
   {                                                                                           \
-    const int ph = (t - b.cz0) & 3;                                                           \
-    const float* wz = T.w[2] + 4 * (Z);                                                       \
-    const float w0 = wz[0], w1 = wz[1], w2 = wz[2], w3 = wz[3];                               \
-    const float ws[4] = {ph == 0 ? w0 : ph == 1 ? w3 : ph == 2 ? w2 : w1,                     \
-                         ph == 0 ? w1 : ph == 1 ? w0 : ph == 2 ? w3 : w2,                     \
-                         ph == 0 ? w2 : ph == 1 ? w1 : ph == 2 ? w0 : w3,                     \
-                         ph == 0 ? w3 : ph == 1 ? w2 : ph == 2 ? w1 : w0};                    \
+    const float* ws = T.w[2] + 4 * (Z);                                                       \
     _Pragma("unroll") for (int k = 0; k < 4; ++k)                                             \
       _Pragma("unroll") for (int r = 0; r < kGzRows; ++r) {                                   \
         acc[k][r].x = fmaf(ws[k], D[r].x, acc[k][r].x);                                       \
@@ -378,7 +383,7 @@ __global__ __launch_bounds__(kGzThreads) __attribute__((amdgpu_waves_per_eu(6)))
     }                                                                                         \
     ahead += plane;                                                                           \
     if ((Z) + 1 == tend && (Z) + 1 < b.ze) {                                                  \
-      BSI_GZ_EMIT(t - b.cz0, ph, false)                                                       \
+      BSI_GZ_EMIT(t - b.cz0, t & 3, false)                                                    \
       ++t;                                                                                    \
       tend = T.first[2][t + 1];                                                               \
     }                                                                                         \
@@ -408,8 +413,9 @@ __global__ __launch_bounds__(kGzThreads) __attribute__((amdgpu_waves_per_eu(6)))
 #undef BSI_GZ_PLANE
   // the brick's last four control planes, t .. t + 3, in ascending order
 #pragma unroll 1
-  for (int n = 0; n < 4; ++n) BSI_GZ_EMIT(t - b.cz0 + n, (t - b.cz0 + n) & 3, n == 3)
+  for (int n = 0; n < 4; ++n) BSI_GZ_EMIT(t - b.cz0 + n, (t + n) & 3, n == 3)
 #undef BSI_GZ_EMIT
+#undef BSI_GZ_PUT_SLOT
 }
 
 // Pass 2: one thread per control point; a wave takes 64 points of one (cy, cz) row.
