@@ -60,10 +60,7 @@ constexpr int kNumFwdShapes = 3;
 static const char* const kFwdShapeName[kNumFwdShapes] = {"4x1", "2x2", "8x1"};
 static const int kFwdShapeWidth[kNumFwdShapes] = {64, 128, 64};
 static const int kFwdShapeRows[kNumFwdShapes] = {4, 2, 8};
-#ifndef BSI_FWD_ITEMS_LIST
-#define BSI_FWD_ITEMS_LIST 512, 2048, 8192
-#endif
-static const int kFwdItems[] = {BSI_FWD_ITEMS_LIST};  // forward items per volume (the z split aims at this)
+static const int kFwdItems[] = {512, 2048, 8192};  // forward items per volume (the z split aims at this)
 static const int kFwdPerCu[] = {0, 2, 4, 8};       // forward workgroups per CU (0: one per item)
 static const int kAdjPerCu[] = {0, 1, 2, 3};       // pass-1 workgroups per CU (0: one per brick)
 static const int kPtsPerCu[] = {0, 8};             // pass-2 workgroups per CU (0: one per block)
@@ -807,9 +804,12 @@ int32_t bsi_batch_tune(bsi_batch* p, hipStream_t stream) {
   // Each candidate is timed the way the plan runs in the end: captured into a
   // graph (on a stream of the tuner's own, since `stream` may be the null
   // stream, which cannot capture) and replayed on `stream`.  Median of 7
-  // replays after one warm-up replay; each replay is waited for, so the device
-  // is idle whenever set_config rewrites the forward's table.
+  // replays after one warm-up replay.  The previous candidate's graph is
+  // dropped, and the tables rewritten, only after a device synchronisation
+  // (as quiesce does): an executable graph is never destroyed while a replay
+  // of it may still be in flight.
   auto time_config = [&](const BatchConfig& c, float* ms) -> int32_t {
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "synchronising before a tuning graph");
     int32_t r = set_config(p, c);
     if (r) return r;
     if ((r = build_graph(p, cap))) return r;
@@ -868,8 +868,9 @@ int32_t bsi_batch_tune(bsi_batch* p, hipStream_t stream) {
     if ((rc = time_config(best, &again)) == BSI_OK && (rc = time_config(start, &base)) == BSI_OK && base <= again)
       best = start;
   }
-  if (rc != BSI_OK) (void)hipDeviceSynchronize();  // a failed candidate may have left work behind
-  else if ((e = hipStreamSynchronize(stream)) != hipSuccess) rc = hip_fail(e, "finishing the tuning runs");
+  // the last tuning graph's replays end before it is dropped and the capture
+  // stream is destroyed
+  if ((e = hipDeviceSynchronize()) != hipSuccess && rc == BSI_OK) rc = hip_fail(e, "finishing the tuning runs");
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   (void)hipStreamDestroy(cap);
