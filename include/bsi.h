@@ -296,9 +296,8 @@ int32_t bsi_batch_bind(bsi_batch* plan, const float* const* grids, float* const*
    it, whether the forward's stores are ordinary or non-temporal, and whether
    pass 1 runs one launch per x-spacing class or one launch for all the
    spacings 4..12 (a kernel that takes the spacing at run time).  The search
-   is a coordinate descent from the current schedule, each candidate captured
-   into a graph (on a stream the tuner creates and destroys) and timed as the
-   median of 7 replays on `stream` after a warm-up replay.  Drops a captured
+   is a coordinate descent from the current schedule, each candidate timed as
+   the median of 5 runs on `stream` after a warm-up run.  Drops a captured
    graph.  The choice is stored in the JSON file named by the environment
    variable BSI_TUNE_CACHE (if set) and read back by later plans with the same
    geometry; BSI_FORCE_CONFIG=<index> skips timing, and an index outside

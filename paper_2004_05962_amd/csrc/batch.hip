@@ -788,41 +788,30 @@ int32_t bsi_batch_tune(bsi_batch* p, hipStream_t stream) {
     return set_config(p, decode_config(v));
   }
   hipEvent_t t0, t1;
-  hipStream_t cap;
   hipError_t e;
   if ((e = hipEventCreate(&t0)) != hipSuccess) return hip_fail(e, "creating a timing event");
   if ((e = hipEventCreate(&t1)) != hipSuccess) {
     (void)hipEventDestroy(t0);
     return hip_fail(e, "creating a timing event");
   }
-  if ((e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking)) != hipSuccess) {
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
-    return hip_fail(e, "creating the capture stream");
-  }
   const bool verbose = std::getenv("BSI_TUNE_VERBOSE") != nullptr;
-  // Each candidate is timed the way the plan runs in the end: captured into a
-  // graph (on a stream of the tuner's own, since `stream` may be the null
-  // stream, which cannot capture) and replayed on `stream`.  Median of 7
-  // replays after one warm-up replay.  The previous candidate's graph is
-  // dropped, and the tables rewritten, only after a device synchronisation
-  // (as quiesce does): an executable graph is never destroyed while a replay
-  // of it may still be in flight.
+  // Median of 5 timed runs after one warm-up run.  Every run ends with the
+  // wait for t1 on `stream`, into which all of the plan's branches join, so
+  // the device is idle whenever set_config rewrites the forward's table.
   auto time_config = [&](const BatchConfig& c, float* ms) -> int32_t {
-    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "synchronising before a tuning graph");
     int32_t r = set_config(p, c);
     if (r) return r;
-    if ((r = build_graph(p, cap))) return r;
-    if ((e = hipGraphLaunch(p->exec, stream)) != hipSuccess) return hip_fail(e, "launching a tuning graph");
-    float times[7];
-    for (int k = 0; k < 7; ++k) {
-      if ((e = hipEventRecord(t0, stream)) != hipSuccess || (e = hipGraphLaunch(p->exec, stream)) != hipSuccess ||
-          (e = hipEventRecord(t1, stream)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess ||
+    if ((r = enqueue(p, stream))) return r;
+    float times[5];
+    for (int k = 0; k < 5; ++k) {
+      if ((e = hipEventRecord(t0, stream)) != hipSuccess) return hip_fail(e, "recording a timing event");
+      if ((r = enqueue(p, stream))) return r;
+      if ((e = hipEventRecord(t1, stream)) != hipSuccess || (e = hipEventSynchronize(t1)) != hipSuccess ||
           (e = hipEventElapsedTime(&times[k], t0, t1)) != hipSuccess)
         return hip_fail(e, "timing a configuration");
     }
-    std::sort(times, times + 7);
-    *ms = times[3];
+    std::sort(times, times + 5);
+    *ms = times[2];
     if (verbose) std::fprintf(stderr, "bsi_batch_tune: %-110s %.4f ms\n", describe_config(c).c_str(), *ms);
     return BSI_OK;
   };
@@ -868,13 +857,9 @@ int32_t bsi_batch_tune(bsi_batch* p, hipStream_t stream) {
     if ((rc = time_config(best, &again)) == BSI_OK && (rc = time_config(start, &base)) == BSI_OK && base <= again)
       best = start;
   }
-  // the last tuning graph's replays end before it is dropped and the capture
-  // stream is destroyed
-  if ((e = hipDeviceSynchronize()) != hipSuccess && rc == BSI_OK) rc = hip_fail(e, "finishing the tuning runs");
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
-  (void)hipStreamDestroy(cap);
-  const int32_t rc2 = set_config(p, rc == BSI_OK ? best : start);  // drops the last tuning graph
+  const int32_t rc2 = set_config(p, rc == BSI_OK ? best : start);
   if (rc == BSI_OK) rc = rc2;
   if (rc == BSI_OK)
     if (const char* path = std::getenv("BSI_TUNE_CACHE")) cache_store(path, p->key, encode_config(p->cfg));
