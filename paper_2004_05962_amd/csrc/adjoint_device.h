@@ -496,14 +496,20 @@ __device__ __forceinline__ void adj_brick(const float* __restrict__ dfield, floa
     case 2: BSI_ADJ_PUT_SLOT(2) break;                                                   \
     default: BSI_ADJ_PUT_SLOT(3) break;                                                  \
   }
+// The emission runs at raised wave priority: the work before and after the
+// tile's barrier then takes issue slots ahead of waves that are only streaming
+// planes (they wait on memory anyway), so the workgroup's waves reach the
+// barrier sooner.
 #define BSI_ADJ_EMIT(CZL, PH, LAST)                                                        \
   {                                                                                      \
+    __builtin_amdgcn_s_setprio(2);                                                       \
     wave_lds_sync(); /* this wave's x-contraction of the previous plane is done with F */ \
     BSI_ADJ_PUT(PH)                                                                      \
     wave_lds_sync();                                                                     \
     adj_emit_xf<DX, R>(b, sm, lut, dx, tid, (CZL));                                      \
     __syncthreads();                                                                     \
     adj_emit_y<DX, kAdjWaves, StageAll>(a, b, pbase, sm, lut, tid, (CZL), (LAST));       \
+    __builtin_amdgcn_s_setprio(0);                                                       \
   }
 
 // One voxel plane Z from register set D: z-accumulation, the loads of the
